@@ -1,0 +1,182 @@
+"""Plain FP64 CPU oracle for the FMM cell-to-cell interaction kernels.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package. The library in
+``paper_2303_08058_amd`` never imports, links or calls it, and it shares no
+code with that library.
+
+The arithmetic lives in ``ot_oracle.c`` (plain C99 + OpenMP, no fast-math);
+this module compiles it with gcc and marshals numpy arrays through ctypes.
+Definitions and pins are documented in the C file's header.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = [os.path.join(_HERE, "ot_oracle.c"), os.path.join(_HERE, "core.inc")]
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NM = 20
+SUB3 = 512
+HALO3 = 13824
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ot_oracle.c into liboracle.so next to it (gcc, -O2, no fast-math)."""
+    if not force and os.path.exists(_LIB):
+        newest = max(os.path.getmtime(p) for p in _SRC)
+        if os.path.getmtime(_LIB) >= newest:
+            return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-std=gnu99", "-Wall", "-o", tmp, _SRC[0], "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    build(force=False)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i = ctypes.c_int
+    lib.orc_multi_index.argtypes = [i, P]
+    lib.orc_green.argtypes = [P, i, P]
+    lib.orc_in_stencil.argtypes = [P, P]
+    lib.orc_in_stencil.restype = i
+    lib.orc_max_threads.restype = i
+    lib.orc_block_forward.argtypes = [P, i, P, i, P, P, i]
+    lib.orc_block_forward.restype = i
+    lib.orc_batched_forward.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
+    lib.orc_batched_forward.restype = i
+    lib.orc_batched_forward_cs.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
+    lib.orc_batched_forward_cs.restype = i
+    lib.orc_batched_backward.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
+    lib.orc_batched_backward.restype = i
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def max_threads() -> int:
+    return _load().orc_max_threads()
+
+
+def multi_index(g: int):
+    out = np.zeros(3, np.int32)
+    _load().orc_multi_index(g, _ptr(out))
+    return tuple(int(v) for v in out)
+
+
+def green(r, order: int = 4) -> np.ndarray:
+    """All derivatives d^gamma(-1/|r|) for |gamma| <= order, graded-lex order."""
+    n = (order + 1) * (order + 2) * (order + 3) // 6
+    r = _f64(r)
+    out = np.zeros(n, np.float64)
+    _load().orc_green(_ptr(r), order, _ptr(out))
+    return out
+
+
+def in_stencil(hi, hj) -> bool:
+    a = _i32(hi)
+    b = _i32(hj)
+    return bool(_load().orc_in_stencil(_ptr(a), _ptr(b)))
+
+
+def block_forward(M, X, mmax: int = 3, want_abs: bool = False, nthreads: int = 0):
+    """Single 24^3 halo block. M: (nm, 13824) with nm in {1, 20}; X: (3, 13824).
+    Returns L (20, 512) [and A (20, 512), the sum of term magnitudes]."""
+    M = _f64(M).reshape(-1, HALO3)
+    X = _f64(X).reshape(3, HALO3)
+    L = np.zeros((NM, SUB3), np.float64)
+    A = np.zeros((NM, SUB3), np.float64) if want_abs else None
+    rc = _load().orc_block_forward(_ptr(M), M.shape[0], _ptr(X), mmax, _ptr(L), _ptr(A),
+                                   nthreads)
+    if rc:
+        raise ValueError("orc_block_forward rejected its arguments")
+    return (L, A) if want_abs else L
+
+
+def _batch_args(batch):
+    tgt = _i32(batch["tgt"])
+    nbr = _i32(batch["nbr"]).reshape(-1, 27)
+    shift = batch.get("shift")
+    period = batch.get("period")
+    shift = None if shift is None else np.ascontiguousarray(shift, dtype=np.int8)
+    period = None if period is None else _f64(period)
+    return int(batch["S"]), int(batch["T"]), tgt, nbr, shift, period
+
+
+def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0):
+    """Batched forward over a selection of targets. Returns L (20, nsel*512)."""
+    S, T, tgt, nbr, shift, period = _batch_args(batch)
+    tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
+    M = _f64(M)
+    X = _f64(X)
+    assert M.shape == (NM, S * SUB3) and X.shape == (3, S * SUB3)
+    L = np.zeros((NM, len(tsel) * SUB3), np.float64)
+    A = np.zeros_like(L) if want_abs else None
+    rc = _load().orc_batched_forward(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period),
+                                     _ptr(M), _ptr(X), _ptr(tsel), len(tsel), _ptr(L),
+                                     _ptr(A), nthreads)
+    if rc:
+        raise ValueError("orc_batched_forward rejected its arguments")
+    return (L, A) if want_abs else L
+
+
+def batched_forward_cs(batch, M, Xre, Xim, tsel=None, nthreads: int = 0):
+    """Complex-position forward (for complex-step derivatives). Returns (Lre, Lim)."""
+    S, T, tgt, nbr, shift, period = _batch_args(batch)
+    tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
+    M = _f64(M)
+    Xre = _f64(Xre)
+    Xim = _f64(Xim)
+    Lre = np.zeros((NM, len(tsel) * SUB3), np.float64)
+    Lim = np.zeros_like(Lre)
+    rc = _load().orc_batched_forward_cs(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift),
+                                        _ptr(period), _ptr(M), _ptr(Xre), _ptr(Xim),
+                                        _ptr(tsel), len(tsel), _ptr(Lre), _ptr(Lim),
+                                        nthreads)
+    if rc:
+        raise ValueError("orc_batched_forward_cs rejected its arguments")
+    return Lre, Lim
+
+
+def batched_backward(batch, M, X, gL, ssel=None, nthreads: int = 0):
+    """Gradients of sum(gL * L) w.r.t. moments and centres of mass of the
+    selected store sub-grids. Returns gM (20, nsel*512), gX (3, nsel*512)."""
+    S, T, tgt, nbr, shift, period = _batch_args(batch)
+    ssel = np.arange(S, dtype=np.int32) if ssel is None else _i32(ssel)
+    M = _f64(M)
+    X = _f64(X)
+    gL = _f64(gL)
+    assert gL.shape == (NM, T * SUB3)
+    gM = np.zeros((NM, len(ssel) * SUB3), np.float64)
+    gX = np.zeros((3, len(ssel) * SUB3), np.float64)
+    rc = _load().orc_batched_backward(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period),
+                                      _ptr(M), _ptr(X), _ptr(gL), _ptr(ssel), len(ssel),
+                                      _ptr(gM), _ptr(gX), nthreads)
+    if rc:
+        raise ValueError("orc_batched_backward rejected its arguments")
+    return gM, gX

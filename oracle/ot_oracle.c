@@ -1,0 +1,522 @@
+/*
+ * ot_oracle.c -- plain FP64 CPU oracle for the FMM cell-to-cell gravity
+ * interaction kernels. TEST INFRASTRUCTURE ONLY: it is called by the tests,
+ * by the smoke check and by the CPU-baseline leg of the benchmark, never by
+ * the library. It shares no code, header, table or generator with the HIP
+ * path.
+ *
+ * What it computes (paper Sec. 2.1: Octo-Tiger's gravity solver is a fast
+ * multipole method on an octree of 8x8x8 sub-grids; Sec. 2.2.1 / 2.3: each
+ * compute kernel works on one sub-grid plus its ghost layers; Sec. 2.2.4:
+ * kernels for many sub-grids may be aggregated into one launch):
+ *
+ *   For every target cell i of a target sub-grid and every alpha, |alpha|<=3,
+ *     L_alpha(i) = sum_{j in S(i)} sum_{|beta| <= 3-|alpha|}
+ *                        s_beta M_beta(j) G_{alpha+beta}(X_i - X_j)
+ *   G(r) = -1/|r|, G_gamma = d^gamma G, s_beta = (-1)^{|beta|}/beta!,
+ *   M_beta(j) = raw Cartesian moments of cell j about its centre of mass X_j,
+ *   S(i) = cells j of the 3x3x3 sub-grid neighbourhood (24^3 halo block) with
+ *          |j - i|_2 > 4  and  |floor(j/2) - floor(i/2)|_2 <= 4  (integer
+ *          cell coordinates), whose sub-grid is available.
+ *
+ * The method reaches exactly this sum (no approximation beyond the stated
+ * truncation), so the oracle is that sum written out: a loop over target
+ * cells, a brute-force test of the criterion for every candidate source, and
+ * the plain double sum over (alpha, beta). The adjoint is the chain rule
+ * applied to the same definition, pair by pair.
+ *
+ * Component order of every 20- or 35-vector: graded lexicographic with x most
+ * significant (1; x,y,z; xx,xy,xz,yy,yz,zz; xxx,xxy,...,zzz; xxxx,...).
+ *
+ * Pins (tests/test_oracle_*.py): closed forms of G against symbolic
+ * differentiation, Laplace trace identities, the lattice-point count of the
+ * stencil, single-source closed forms, direct summation over point masses
+ * with the error shrinking at the rate of the omitted order, eight symmetric
+ * children = monopole, Newton's third law, translation and reflection
+ * symmetry, 30-digit evaluation, and for the adjoint: dot-product test,
+ * complex-step derivatives and translation invariance.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NM 20  /* moments / outputs, |beta| <= 3 */
+#define NG3 20 /* derivatives up to order 3 */
+#define NG 35  /* derivatives up to order 4 */
+#define SUB 8
+#define SUB3 512
+#define HALO 24
+#define HALO3 13824
+
+/* ---------------------------------------------------------------------------
+ * Multi-index bookkeeping (enumerated at start-up, graded lexicographic)
+ * ------------------------------------------------------------------------- */
+static int g_exp[NG][3];
+static int g_ord[NG];
+static int g_nax[NG], g_ax[NG][4];
+static int g_sum[NG][NG];    /* index of gamma + delta, -1 if the order exceeds 4 */
+static double g_tsign[NG];   /* s_beta = (-1)^{|beta|} / beta! */
+static int g_ready = 0;
+
+static double factorial(int n)
+{
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+static int find_index(int a, int b, int c)
+{
+    for (int g = 0; g < NG; ++g)
+        if (g_exp[g][0] == a && g_exp[g][1] == b && g_exp[g][2] == c) return g;
+    return -1;
+}
+
+static void init_tables(void)
+{
+    if (g_ready) return;
+    int k = 0;
+    for (int n = 0; n <= 4; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                g_exp[k][0] = a;
+                g_exp[k][1] = b;
+                g_exp[k][2] = n - a - b;
+                ++k;
+            }
+    for (int g = 0; g < NG; ++g) {
+        g_ord[g] = g_exp[g][0] + g_exp[g][1] + g_exp[g][2];
+        /* axis list, e.g. xxy -> {0,0,1} */
+        int m = 0;
+        for (int d = 0; d < 3; ++d)
+            for (int e = 0; e < g_exp[g][d]; ++e) g_ax[g][m++] = d;
+        g_nax[g] = m;
+        double bf = factorial(g_exp[g][0]) * factorial(g_exp[g][1]) * factorial(g_exp[g][2]);
+        g_tsign[g] = ((g_ord[g] % 2) ? -1.0 : 1.0) / bf;
+    }
+    for (int g = 0; g < NG; ++g)
+        for (int h = 0; h < NG; ++h)
+            g_sum[g][h] = find_index(g_exp[g][0] + g_exp[h][0], g_exp[g][1] + g_exp[h][1],
+                                     g_exp[g][2] + g_exp[h][2]);
+    g_ready = 1;
+}
+
+static int ncomp(int order) { return (order + 1) * (order + 2) * (order + 3) / 6; }
+static int order_of(int g) { return g_ord[g]; }
+static int index_of(int a, int b, int c) { return find_index(a, b, c); }
+static int sum_index(int g, int h) { return g_sum[g][h]; }
+static double taylor_sign(int g) { return g_tsign[g]; }
+
+/* axis list of component g; returns its length */
+static int axes_of(int g, int ax[4])
+{
+    for (int m = 0; m < g_nax[g]; ++m) ax[m] = g_ax[g][m];
+    return g_nax[g];
+}
+
+static double delta(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+/* ---------------------------------------------------------------------------
+ * Opening criterion on integer halo-block coordinates (all >= 0)
+ * ------------------------------------------------------------------------- */
+static int in_stencil(const int hi[3], const int hj[3])
+{
+    int d2 = 0, p2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        int d = hj[k] - hi[k];
+        int p = hj[k] / 2 - hi[k] / 2;
+        d2 += d * d;
+        p2 += p * p;
+    }
+    return d2 > 16 && p2 <= 16;
+}
+
+/* slot = sx + 3 sy + 9 sz, s in {0,1,2} <-> neighbour offset -1, 0, +1 */
+static void slot_coords(int slot, int s[3])
+{
+    s[0] = slot % 3;
+    s[1] = (slot / 3) % 3;
+    s[2] = slot / 9;
+}
+
+static void local_coords(int c, int l[3])
+{
+    l[0] = c % SUB;
+    l[1] = (c / SUB) % SUB;
+    l[2] = c / (SUB * SUB);
+}
+
+/* ---------------------------------------------------------------------------
+ * Scalar-generic core: real and complex instantiations
+ * ------------------------------------------------------------------------- */
+#define SC double
+#define SQRT sqrt
+#define FN(x) x##_re
+#define cabs_generic(v) fabs(v)
+#include "core.inc"
+#undef SC
+#undef SQRT
+#undef FN
+#undef cabs_generic
+
+#define SC double _Complex
+#define SQRT csqrt
+#define FN(x) x##_cx
+#define cabs_generic(v) cabs(v)
+#include "core.inc"
+#undef SC
+#undef SQRT
+#undef FN
+#undef cabs_generic
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+/* ---------------------------------------------------------------------------
+ * Exported helpers (for the pins)
+ * ------------------------------------------------------------------------- */
+void orc_multi_index(int g, int out[3])
+{
+    init_tables();
+    out[0] = g_exp[g][0];
+    out[1] = g_exp[g][1];
+    out[2] = g_exp[g][2];
+}
+
+void orc_green(const double r[3], int order, double *G)
+{
+    init_tables();
+    green_re(r, order, G);
+}
+
+int orc_in_stencil(const int hi[3], const int hj[3]) { return in_stencil(hi, hj); }
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------------
+ * Single sub-grid form: 24^3 halo block, SoA, cell index x + 24 y + 576 z.
+ * M[nm][13824] raw moments (nm = 1: monopole masses, nm = 20: moments up to
+ * order 3), X[3][13824] centres of mass; L[20][512] for the central 8^3
+ * (index x + 8 y + 64 z). All halo cells are available.
+ * ------------------------------------------------------------------------- */
+int orc_block_forward(const double *M, int nm, const double *X, int mmax, double *L,
+                      double *Aabs, int nthreads)
+{
+    init_tables();
+    if (nm != 1 && nm != NM) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int ci = 0; ci < SUB3; ++ci) {
+        int li[3];
+        local_coords(ci, li);
+        int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+        int iidx = hi[0] + HALO * hi[1] + HALO * HALO * hi[2];
+        double Xi[3] = {X[iidx], X[HALO3 + iidx], X[2 * HALO3 + iidx]};
+        double acc[NM] = {0};
+        double aabs[NM] = {0};
+        for (int jz = 0; jz < HALO; ++jz)
+            for (int jy = 0; jy < HALO; ++jy)
+                for (int jx = 0; jx < HALO; ++jx) {
+                    int hj[3] = {jx, jy, jz};
+                    if (!in_stencil(hi, hj)) continue;
+                    int jidx = jx + HALO * jy + HALO * HALO * jz;
+                    double Xj[3] = {X[jidx], X[HALO3 + jidx], X[2 * HALO3 + jidx]};
+                    double Mj[NM];
+                    for (int b = 0; b < nm; ++b) Mj[b] = M[(size_t)b * HALO3 + jidx];
+                    pair_forward_re(Xi, Xj, Mj, nm, mmax, acc, Aabs ? aabs : NULL);
+                }
+        for (int a = 0; a < NM; ++a) {
+            L[a * SUB3 + ci] = acc[a];
+            if (Aabs) Aabs[a * SUB3 + ci] = aabs[a];
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Batched form (store of S sub-grids, T targets).
+ *   M[20][S*512], X[3][S*512]: cell c of store sub-grid s at s*512 + c.
+ *   tgt[T]: store id of each target; nbr[T][27]: store id of the sub-grid in
+ *   each neighbour slot (slot 13 = the target itself), -1 = not available
+ *   (pairs with sources there are dropped).
+ *   shift[T][27][3] (may be NULL): periodic image shift of the neighbour, in
+ *   units of period[3]; the source centre used is X_j + shift * period.
+ * Outputs are compact over a selection tsel[nsel] of target indices:
+ *   L[20][nsel*512].
+ * ------------------------------------------------------------------------- */
+static int check_batch(int S, int T, const int32_t *tgt, const int32_t *nbr)
+{
+    if (S <= 0 || T <= 0 || !tgt || !nbr) return -1;
+    for (int t = 0; t < T; ++t) {
+        if (tgt[t] < 0 || tgt[t] >= S) return -1;
+        for (int s = 0; s < 27; ++s)
+            if (nbr[t * 27 + s] < -1 || nbr[t * 27 + s] >= S) return -1;
+        if (nbr[t * 27 + 13] != tgt[t]) return -1;
+    }
+    return 0;
+}
+
+static void neighbour_shift(const int8_t *shift, const double *period, int t, int slot,
+                            double sh[3])
+{
+    for (int k = 0; k < 3; ++k)
+        sh[k] = (shift && period) ? (double)shift[((size_t)t * 27 + slot) * 3 + k] * period[k]
+                                  : 0.0;
+}
+
+int orc_batched_forward(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                        const int8_t *shift, const double *period, const double *M,
+                        const double *X, const int32_t *tsel, int nsel, double *L,
+                        double *Aabs, int nthreads)
+{
+    init_tables();
+    if (check_batch(S, T, tgt, nbr)) return -1;
+    for (int q = 0; q < nsel; ++q)
+        if (tsel[q] < 0 || tsel[q] >= T) return -1;
+    const size_t NS = (size_t)S * SUB3;
+    const size_t NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int q = 0; q < nsel; ++q)
+        for (int ci = 0; ci < SUB3; ++ci) {
+            int t = tsel[q];
+            int li[3];
+            local_coords(ci, li);
+            int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+            size_t iidx = (size_t)tgt[t] * SUB3 + ci;
+            double Xi[3] = {X[iidx], X[NS + iidx], X[2 * NS + iidx]};
+            double acc[NM] = {0}, aabs[NM] = {0};
+            for (int slot = 0; slot < 27; ++slot) {
+                int blk = nbr[t * 27 + slot];
+                if (blk < 0) continue;
+                int so[3];
+                slot_coords(slot, so);
+                double sh[3];
+                neighbour_shift(shift, period, t, slot, sh);
+                for (int cj = 0; cj < SUB3; ++cj) {
+                    int lj[3];
+                    local_coords(cj, lj);
+                    int hj[3] = {8 * so[0] + lj[0], 8 * so[1] + lj[1], 8 * so[2] + lj[2]};
+                    if (!in_stencil(hi, hj)) continue;
+                    size_t jidx = (size_t)blk * SUB3 + cj;
+                    double Xj[3] = {X[jidx] + sh[0], X[NS + jidx] + sh[1],
+                                    X[2 * NS + jidx] + sh[2]};
+                    double Mj[NM];
+                    for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
+                    pair_forward_re(Xi, Xj, Mj, NM, 3, acc, Aabs ? aabs : NULL);
+                }
+            }
+            for (int a = 0; a < NM; ++a) {
+                L[a * NO + (size_t)q * SUB3 + ci] = acc[a];
+                if (Aabs) Aabs[a * NO + (size_t)q * SUB3 + ci] = aabs[a];
+            }
+        }
+    return 0;
+}
+
+/* Same sum with complex centres of mass X = Xre + i Xim (moments real), for
+ * complex-step differentiation: d(sum w L)/dX_c,k = Im(sum w L(X + i h e_ck))/h. */
+int orc_batched_forward_cs(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                           const int8_t *shift, const double *period, const double *M,
+                           const double *Xre, const double *Xim, const int32_t *tsel,
+                           int nsel, double *Lre, double *Lim, int nthreads)
+{
+    init_tables();
+    if (check_batch(S, T, tgt, nbr)) return -1;
+    for (int q = 0; q < nsel; ++q)
+        if (tsel[q] < 0 || tsel[q] >= T) return -1;
+    const size_t NS = (size_t)S * SUB3;
+    const size_t NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int q = 0; q < nsel; ++q)
+        for (int ci = 0; ci < SUB3; ++ci) {
+            int t = tsel[q];
+            int li[3];
+            local_coords(ci, li);
+            int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+            size_t iidx = (size_t)tgt[t] * SUB3 + ci;
+            double _Complex Xi[3];
+            for (int k = 0; k < 3; ++k) Xi[k] = Xre[k * NS + iidx] + I * Xim[k * NS + iidx];
+            double _Complex acc[NM];
+            for (int a = 0; a < NM; ++a) acc[a] = 0;
+            for (int slot = 0; slot < 27; ++slot) {
+                int blk = nbr[t * 27 + slot];
+                if (blk < 0) continue;
+                int so[3];
+                slot_coords(slot, so);
+                double sh[3];
+                neighbour_shift(shift, period, t, slot, sh);
+                for (int cj = 0; cj < SUB3; ++cj) {
+                    int lj[3];
+                    local_coords(cj, lj);
+                    int hj[3] = {8 * so[0] + lj[0], 8 * so[1] + lj[1], 8 * so[2] + lj[2]};
+                    if (!in_stencil(hi, hj)) continue;
+                    size_t jidx = (size_t)blk * SUB3 + cj;
+                    double _Complex Xj[3];
+                    for (int k = 0; k < 3; ++k)
+                        Xj[k] = (Xre[k * NS + jidx] + sh[k]) + I * Xim[k * NS + jidx];
+                    double Mj[NM];
+                    for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
+                    pair_forward_cx(Xi, Xj, Mj, NM, 3, acc, NULL);
+                }
+            }
+            for (int a = 0; a < NM; ++a) {
+                Lre[a * NO + (size_t)q * SUB3 + ci] = creal(acc[a]);
+                Lim[a * NO + (size_t)q * SUB3 + ci] = cimag(acc[a]);
+            }
+        }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Adjoint of the batched form for the loss  l = sum_t sum_i sum_alpha
+ * gL_alpha(t, i) L_alpha(t, i)  (gL[20][T*512] = dl/dL).
+ *
+ * For one pair (target i of target t, source j) with r = X_i - (X_j + shift):
+ *   P = sum_{|a|+|b|<=3} w_a(i) s_b M_b(j) G_{a+b}(r)
+ *   dP/dM_b(j) = s_b sum_{|a|<=3-|b|} w_a(i) G_{a+b}(r)
+ *   dP/dX_i,k  = + sum_{a,b} w_a(i) s_b M_b(j) G_{a+b+e_k}(r)
+ *   dP/dX_j,k  = - (same sum)
+ * The gradients of a store cell c are the sums over every pair in which c is
+ * the source and every pair in which c is the target. The loops below visit
+ * those pairs from c's side (so that any subset of store sub-grids can be
+ * evaluated on its own); the summand of each pair is the chain rule above.
+ * Outputs are compact over a selection ssel[nsel] of store sub-grids:
+ *   gM[20][nsel*512], gX[3][nsel*512].
+ * ------------------------------------------------------------------------- */
+static void pair_gradients(const double Xi[3], const double Xj[3], const double *w,
+                           const double *Mj, double dM[NM], double dX[3])
+{
+    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
+    double G[NG];
+    green_re(r, 4, G);
+    int ek[3] = {index_of(1, 0, 0), index_of(0, 1, 0), index_of(0, 0, 1)};
+    for (int b = 0; b < NM; ++b) dM[b] = 0.0;
+    dX[0] = dX[1] = dX[2] = 0.0;
+    for (int a = 0; a < NM; ++a)
+        for (int b = 0; b < NM; ++b) {
+            if (order_of(a) + order_of(b) > 3) continue;
+            int ab = sum_index(a, b);
+            dM[b] += taylor_sign(b) * w[a] * G[ab];
+            for (int k = 0; k < 3; ++k)
+                dX[k] += w[a] * taylor_sign(b) * Mj[b] * G[sum_index(ab, ek[k])];
+        }
+}
+
+int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                         const int8_t *shift, const double *period, const double *M,
+                         const double *X, const double *gL, const int32_t *ssel, int nsel,
+                         double *gM, double *gX, int nthreads)
+{
+    init_tables();
+    if (check_batch(S, T, tgt, nbr)) return -1;
+    for (int q = 0; q < nsel; ++q)
+        if (ssel[q] < 0 || ssel[q] >= S) return -1;
+    const size_t NS = (size_t)S * SUB3;
+    const size_t NT = (size_t)T * SUB3;
+    const size_t NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < nsel; ++q) {
+        int s = ssel[q];
+        /* every (target, slot) that sees sub-grid s as a source, and every
+         * target whose own sub-grid is s -- found by plain search */
+        int nrel = 0, cap = 64;
+        int *rel_t = malloc(sizeof(int) * cap), *rel_slot = malloc(sizeof(int) * cap);
+        for (int t = 0; t < T; ++t)
+            for (int slot = 0; slot < 27; ++slot)
+                if (nbr[t * 27 + slot] == s) {
+                    if (nrel == cap) {
+                        cap *= 2;
+                        rel_t = realloc(rel_t, sizeof(int) * cap);
+                        rel_slot = realloc(rel_slot, sizeof(int) * cap);
+                    }
+                    rel_t[nrel] = t;
+                    rel_slot[nrel] = slot;
+                    ++nrel;
+                }
+        for (int cc = 0; cc < SUB3; ++cc) {
+            int lc[3];
+            local_coords(cc, lc);
+            size_t cidx = (size_t)s * SUB3 + cc;
+            double Xc[3] = {X[cidx], X[NS + cidx], X[2 * NS + cidx]};
+            double Mc[NM];
+            for (int b = 0; b < NM; ++b) Mc[b] = M[b * NS + cidx];
+            double accM[NM] = {0}, accX[3] = {0, 0, 0};
+            double dM[NM], dX[3], w[NM];
+            /* (a) c as a source of target cells of target t, seen at `slot` */
+            for (int e = 0; e < nrel; ++e) {
+                int t = rel_t[e], slot = rel_slot[e];
+                int so[3];
+                slot_coords(slot, so);
+                int hj[3] = {8 * so[0] + lc[0], 8 * so[1] + lc[1], 8 * so[2] + lc[2]};
+                double sh[3];
+                neighbour_shift(shift, period, t, slot, sh);
+                double Xj[3] = {Xc[0] + sh[0], Xc[1] + sh[1], Xc[2] + sh[2]};
+                for (int ci = 0; ci < SUB3; ++ci) {
+                    int li[3];
+                    local_coords(ci, li);
+                    int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+                    if (!in_stencil(hi, hj)) continue;
+                    size_t iidx = (size_t)tgt[t] * SUB3 + ci;
+                    double Xi[3] = {X[iidx], X[NS + iidx], X[2 * NS + iidx]};
+                    for (int a = 0; a < NM; ++a) w[a] = gL[a * NT + (size_t)t * SUB3 + ci];
+                    pair_gradients(Xi, Xj, w, Mc, dM, dX);
+                    for (int b = 0; b < NM; ++b) accM[b] += dM[b];
+                    for (int k = 0; k < 3; ++k) accX[k] -= dX[k];
+                }
+            }
+            /* (b) c as a target cell of every target t whose sub-grid is s */
+            for (int t = 0; t < T; ++t) {
+                if (tgt[t] != s) continue;
+                int hi[3] = {lc[0] + 8, lc[1] + 8, lc[2] + 8};
+                for (int a = 0; a < NM; ++a) w[a] = gL[a * NT + (size_t)t * SUB3 + cc];
+                for (int slot = 0; slot < 27; ++slot) {
+                    int blk = nbr[t * 27 + slot];
+                    if (blk < 0) continue;
+                    int so[3];
+                    slot_coords(slot, so);
+                    double sh[3];
+                    neighbour_shift(shift, period, t, slot, sh);
+                    for (int cj = 0; cj < SUB3; ++cj) {
+                        int lj[3];
+                        local_coords(cj, lj);
+                        int hj[3] = {8 * so[0] + lj[0], 8 * so[1] + lj[1], 8 * so[2] + lj[2]};
+                        if (!in_stencil(hi, hj)) continue;
+                        size_t jidx = (size_t)blk * SUB3 + cj;
+                        double Xj[3] = {X[jidx] + sh[0], X[NS + jidx] + sh[1],
+                                        X[2 * NS + jidx] + sh[2]};
+                        double Mj[NM];
+                        for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
+                        pair_gradients(Xc, Xj, w, Mj, dM, dX);
+                        for (int k = 0; k < 3; ++k) accX[k] += dX[k];
+                    }
+                }
+            }
+            for (int b = 0; b < NM; ++b) gM[b * NO + (size_t)q * SUB3 + cc] = accM[b];
+            for (int k = 0; k < 3; ++k) gX[k * NO + (size_t)q * SUB3 + cc] = accX[k];
+        }
+        free(rel_t);
+        free(rel_slot);
+    }
+    return 0;
+}
