@@ -1,0 +1,156 @@
+/*
+ * ot_fmm.h -- C ABI of the MI355X (gfx950) FP64 fast-multipole cell-to-cell
+ * gravity interaction kernels.
+ *
+ * The operation (paper Sec. 2.1: the gravity solver of Octo-Tiger is a fast
+ * multipole method on an adaptive octree whose nodes are 8x8x8 sub-grids;
+ * Sec. 2.2.1 and 2.3: every compute kernel works on one sub-grid and its
+ * ghost layers; Sec. 2.2.4: kernels of many sub-grids can be aggregated into
+ * one launch). For every target cell i of a target sub-grid and every
+ * multi-index alpha with |alpha| <= 3 (20 coefficients):
+ *
+ *   L_alpha(i) = sum_{j in S(i)} sum_{|beta| <= 3-|alpha|}
+ *                    (-1)^{|beta|}/beta! * M_beta(j) * d^{alpha+beta} G (X_i - X_j)
+ *
+ *   G(r) = -1/|r| (gravitational constant 1), X = centre of mass of a cell,
+ *   M_beta = raw Cartesian moments of the cell's mass about X (no 1/beta!),
+ *   S(i) = cells j of the 3x3x3 sub-grid neighbourhood of i's sub-grid (the
+ *   24^3 halo block) with |j-i|_2 > 4 and |floor(j/2)-floor(i/2)|_2 <= 4 in
+ *   integer cell coordinates, whose sub-grid is available.
+ * L_alpha are Cartesian derivatives of the potential at X_i (the local Taylor
+ * coefficients without the 1/alpha! factor).
+ *
+ * Conventions shared by every entry point
+ *   - Component order of all 20-vectors: graded lexicographic, x most
+ *     significant: 1; x,y,z; xx,xy,xz,yy,yz,zz; xxx,xxy,xxz,xyy,xyz,xzz,yyy,
+ *     yyz,yzz,zzz. Arrays are structure-of-arrays: component-major.
+ *   - All double pointers are DEVICE pointers (FP64, 8-byte aligned), owned by
+ *     the caller. The library keeps no reference to them after a call returns,
+ *     except inside a captured step graph (ot_fmm_step_graph_create).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). The
+ *     compute calls only enqueue work; they never synchronize or allocate, and
+ *     they may be captured into a hipGraph by the caller.
+ *   - Return value: OT_FMM_OK or a negative error code. On OT_FMM_EINVAL
+ *     nothing was enqueued. Details of the last error of the calling thread
+ *     are available from ot_fmm_last_error(). Device faults surface at the
+ *     caller's next synchronisation.
+ *   - Results are bitwise reproducible run to run for a fixed schedule.
+ */
+#ifndef OT_FMM_H
+#define OT_FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OT_FMM_VERSION 100
+
+enum {
+    OT_FMM_OK = 0,
+    OT_FMM_EINVAL = -1,       /* invalid argument; nothing enqueued */
+    OT_FMM_EHIP = -2,         /* HIP runtime or launch error */
+    OT_FMM_ENOMEM = -3,       /* device allocation failed (plan creation only) */
+    OT_FMM_EUNSUPPORTED = -4  /* current device is not gfx950 / no device */
+};
+
+/* Schedules (how a target sub-grid's 512 cells are spread over wavefronts).
+ * Both keep one work-group per target sub-grid and one staged source z-plane
+ * in LDS; lanes are the 8x8 target cells of one z-plane. */
+enum {
+    OT_FMM_SCHED_AUTO = 0,  /* the plan's tuned choice (ot_fmm_autotune), else the default */
+    OT_FMM_SCHED_W8 = 1,    /* 8 wavefronts: one per target z-plane */
+    OT_FMM_SCHED_W16 = 2    /* 16 wavefronts: two per target z-plane, stencil rows split */
+};
+
+/* ---------------------------------------------------------------------------
+ * Single sub-grid forms (one 24^3 halo block = 3x3x3 sub-grids, all present).
+ * Halo arrays: index x + 24 y + 576 z, x fastest. Output L[20][512] for the
+ * central 8^3 cells (halo coordinates 8..15), index x + 8 y + 64 z.
+ * ------------------------------------------------------------------------- */
+
+/* Monopole kernel (paper Sec. 2.1 gravity FMM; only the mass moment):
+ *   mass[13824], com[3][13824] -> L[20][512] with M_beta = 0 for |beta| > 0. */
+int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stream);
+
+/* Multipole kernel: M[20][13824] raw moments, com[3][13824] -> L[20][512]. */
+int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched forms (paper Sec. 2.2.4: one launch over many sub-grids).
+ *
+ * A store holds S sub-grids: M[20][S*512], com[3][S*512]; cell c = x+8y+64z
+ * of store sub-grid s lives at s*512 + c. T target sub-grids are given by
+ *   tgt[T]       store id of each target (distinct),
+ *   nbr[T][27]   store id of the sub-grid in each neighbour slot
+ *                slot = sx + 3 sy + 9 sz, s in {0,1,2} <-> offset -1,0,+1;
+ *                slot 13 must equal tgt[t]; -1 = not available (its pairs are
+ *                dropped),
+ *   shift[T][27][3] (may be NULL) periodic image shift of each neighbour in
+ *                units of period[3]: the source centre used is
+ *                com + shift * period.
+ * The tables are HOST arrays; ot_fmm_plan_create validates them and keeps
+ * device copies plus the inverse (source -> target) relations used by the
+ * adjoint, the work order and the exact pair counts.
+ * Outputs: L[20][T*512] (target t's cells at t*512 + c).
+ * ------------------------------------------------------------------------- */
+typedef struct ot_fmm_plan_s* ot_fmm_plan;
+
+/* Validates the descriptor (EINVAL: S or T <= 0, tgt out of range or
+ * repeated, nbr out of [-1, S), nbr[t][13] != tgt[t], shift without period,
+ * two targets claiming the same (source, slot) relation) and allocates the
+ * device tables (ENOMEM). Synchronous. The plan is bound to the current
+ * device. */
+int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr,
+                       const int8_t* shift, const double* period, ot_fmm_plan* out);
+int ot_fmm_plan_destroy(ot_fmm_plan plan);
+
+/* Exact number of interacting (target cell, source cell) pairs of the plan,
+ * counted from the descriptor (the unit of the throughput metric). */
+int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs);
+
+/* Batched multipole forward: M[20][S*512], com[3][S*512] -> L[20][T*512]. */
+int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                             int sched, void* stream);
+
+/* Adjoint of the batched forward for the loss l = sum gL * L:
+ *   gL[20][T*512] -> gM[20][S*512] = dl/dM, gcom[3][S*512] = dl/dcom.
+ * gM and gcom are OVERWRITTEN; cells of store sub-grids that no target
+ * references get 0. Gather form (no atomics): one pass over each store
+ * sub-grid's source role, then one over each target's own cells. gM/gcom
+ * must not alias M, com or gL. Schedule OT_FMM_SCHED_W8 (or AUTO). */
+int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* com,
+                              const double* gL, double* gM, double* gcom, int sched,
+                              void* stream);
+
+/* Times every schedule of the forward (and backward, if gL/gM/gcom are not
+ * NULL) on the given buffers and stores the fastest in the plan; returns the
+ * choices. Synchronizes `stream`; do not call it while capturing. The buffers
+ * are overwritten with valid results of the last timed schedule. */
+int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                    const double* gL, double* gM, double* gcom, void* stream,
+                    int* fwd_sched, int* bwd_sched);
+
+/* Captures forward (+ backward when gL/gM/gcom are not NULL) with the given
+ * schedules into a hipGraph owned by the plan (replacing any previous one).
+ * The graph bakes in the pointers: re-create it when buffers move. */
+int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                             const double* gL, double* gM, double* gcom, int fwd_sched,
+                             int bwd_sched);
+/* Replays the captured graph on `stream`. EINVAL if none was captured. */
+int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Helpers
+ * ------------------------------------------------------------------------- */
+const char* ot_fmm_strerror(int code);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* ot_fmm_last_error(void);
+int ot_fmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OT_FMM_H */

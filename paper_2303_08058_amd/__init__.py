@@ -1,0 +1,261 @@
+"""MI355X (gfx950) FP64 fast-multipole cell-to-cell interaction kernels.
+
+Thin Python binding of the C ABI in ``include/ot_fmm.h`` (library
+``libotfmm.so`` next to this file, built by ``paper_2303_08058_amd.build``).
+Functions keep the C names and only marshal arguments: device pointers of
+float64 torch tensors and the current HIP stream. Every step of the
+computation runs in the HIP kernels; there is no CPU fallback, and importing
+the package fails if the library has not been built.
+
+Layouts and conventions: see the header (halo blocks [ncomp][13824], stores
+[ncomp][S*512], outputs [20][512] or [20][T*512], components in graded
+lexicographic order).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libotfmm.so")
+
+OT_FMM_OK = 0
+OT_FMM_EINVAL = -1
+OT_FMM_EHIP = -2
+OT_FMM_ENOMEM = -3
+OT_FMM_EUNSUPPORTED = -4
+
+SCHED_AUTO = 0
+SCHED_W8 = 1
+SCHED_W16 = 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libotfmm.so is not built; run `python -m paper_2303_08058_amd.build` "
+        "(the HIP library is required, there is no fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I32 = ctypes.c_int32
+
+_lib.ot_fmm_version.restype = _I
+_lib.ot_fmm_strerror.argtypes = [_I]
+_lib.ot_fmm_strerror.restype = ctypes.c_char_p
+_lib.ot_fmm_last_error.restype = ctypes.c_char_p
+_lib.ot_fmm_monopole.argtypes = [_P, _P, _P, _P]
+_lib.ot_fmm_monopole.restype = _I
+_lib.ot_fmm_multipole.argtypes = [_P, _P, _P, _P]
+_lib.ot_fmm_multipole.restype = _I
+_lib.ot_fmm_plan_create.argtypes = [_I32, _I32, _P, _P, _P, _P, ctypes.POINTER(_P)]
+_lib.ot_fmm_plan_create.restype = _I
+_lib.ot_fmm_plan_destroy.argtypes = [_P]
+_lib.ot_fmm_plan_destroy.restype = _I
+_lib.ot_fmm_plan_pairs.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
+_lib.ot_fmm_plan_pairs.restype = _I
+_lib.ot_fmm_multipole_batched.argtypes = [_P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_batched.restype = _I
+_lib.ot_fmm_multipole_backward.argtypes = [_P, _P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_backward.restype = _I
+_lib.ot_fmm_autotune.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P,
+                                 ctypes.POINTER(_I), ctypes.POINTER(_I)]
+_lib.ot_fmm_autotune.restype = _I
+_lib.ot_fmm_step_graph_create.argtypes = [_P, _P, _P, _P, _P, _P, _P, _I, _I]
+_lib.ot_fmm_step_graph_create.restype = _I
+_lib.ot_fmm_step_graph_launch.argtypes = [_P, _P]
+_lib.ot_fmm_step_graph_launch.restype = _I
+
+
+class OtFmmError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        detail = _lib.ot_fmm_last_error().decode(errors="replace")
+        msg = _lib.ot_fmm_strerror(code).decode()
+        super().__init__("%s: %s (%d)%s" % (where, msg, code, ": " + detail if detail else ""))
+
+
+def _check(rc, where):
+    if rc != OT_FMM_OK:
+        raise OtFmmError(rc, where)
+
+
+def version() -> int:
+    return _lib.ot_fmm_version()
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _dptr(t, shape, name):
+    """Device pointer of a contiguous float64 GPU tensor of the given shape."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 GPU tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# single sub-grid forms
+# ---------------------------------------------------------------------------
+def ot_fmm_monopole(mass, com, L, stream=None):
+    """mass (13824,), com (3, 13824) -> L (20, 512), all float64 on the GPU."""
+    _check(_lib.ot_fmm_monopole(_dptr(mass, (13824,), "mass"), _dptr(com, (3, 13824), "com"),
+                                _dptr(L, (20, 512), "L"), _stream(stream)), "ot_fmm_monopole")
+    return L
+
+
+def ot_fmm_multipole(M, com, L, stream=None):
+    """M (20, 13824), com (3, 13824) -> L (20, 512), all float64 on the GPU."""
+    _check(_lib.ot_fmm_multipole(_dptr(M, (20, 13824), "M"), _dptr(com, (3, 13824), "com"),
+                                 _dptr(L, (20, 512), "L"), _stream(stream)), "ot_fmm_multipole")
+    return L
+
+
+# ---------------------------------------------------------------------------
+# batched forms
+# ---------------------------------------------------------------------------
+class Plan:
+    """Validated batched descriptor with device tables (ot_fmm_plan)."""
+
+    def __init__(self, S, T, tgt, nbr, shift=None, period=None):
+        self.S = int(S)
+        self.T = int(T)
+        tgt = np.ascontiguousarray(tgt, dtype=np.int32)
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        if tgt.shape != (self.T,) or nbr.shape != (self.T, 27):
+            raise ValueError("tgt must be (T,) and nbr (T, 27)")
+        if shift is not None:
+            shift = np.ascontiguousarray(shift, dtype=np.int8)
+            if shift.shape != (self.T, 27, 3):
+                raise ValueError("shift must be (T, 27, 3)")
+        if period is not None:
+            period = np.ascontiguousarray(period, dtype=np.float64)
+            if period.shape != (3,):
+                raise ValueError("period must be (3,)")
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(_lib.ot_fmm_plan_create(
+            self.S, self.T, tgt.ctypes.data_as(_P), nbr.ctypes.data_as(_P),
+            None if shift is None else shift.ctypes.data_as(_P),
+            None if period is None else period.ctypes.data_as(_P), ctypes.byref(h)),
+            "ot_fmm_plan_create")
+        self._h = h
+
+    @classmethod
+    def from_batch(cls, batch):
+        return cls(batch["S"], batch["T"], batch["tgt"], batch["nbr"], batch.get("shift"),
+                   batch.get("period"))
+
+    def close(self):
+        if self._h is not None:
+            _lib.ot_fmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("plan is closed")
+        return self._h
+
+    def pairs(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.ot_fmm_plan_pairs(self.handle, ctypes.byref(v)), "ot_fmm_plan_pairs")
+        return int(v.value)
+
+    def _shapes(self):
+        NS, NT = self.S * 512, self.T * 512
+        return (20, NS), (3, NS), (20, NT)
+
+    def multipole_batched(self, M, com, L, sched=SCHED_AUTO, stream=None):
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_batched(self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"),
+                                             _dptr(L, sl, "L"), int(sched), _stream(stream)),
+               "ot_fmm_multipole_batched")
+        return L
+
+    def multipole_backward(self, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_backward(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(gL, sl, "gL"),
+            _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"), int(sched), _stream(stream)),
+            "ot_fmm_multipole_backward")
+        return gM, gcom
+
+    def autotune(self, M, com, L, gL=None, gM=None, gcom=None, stream=None):
+        sm, sx, sl = self._shapes()
+        f = ctypes.c_int()
+        b = ctypes.c_int()
+        _check(_lib.ot_fmm_autotune(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+            _dptr(gL, sl, "gL"), _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"),
+            _stream(stream), ctypes.byref(f), ctypes.byref(b)), "ot_fmm_autotune")
+        return f.value, b.value
+
+    def step_graph_create(self, M, com, L, gL=None, gM=None, gcom=None, fwd_sched=SCHED_AUTO,
+                          bwd_sched=SCHED_AUTO):
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_step_graph_create(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+            _dptr(gL, sl, "gL"), _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"),
+            int(fwd_sched), int(bwd_sched)), "ot_fmm_step_graph_create")
+
+    def step_graph_launch(self, stream=None):
+        _check(_lib.ot_fmm_step_graph_launch(self.handle, _stream(stream)),
+               "ot_fmm_step_graph_launch")
+
+
+def ot_fmm_multipole_batched(plan, M, com, L, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_batched(M, com, L, sched, stream)
+
+
+def ot_fmm_multipole_backward(plan, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_backward(M, com, gL, gM, gcom, sched, stream)
+
+
+class MultipoleBatched(torch.autograd.Function):
+    """L = multipole_batched(M, com) with the hand-written adjoint as backward.
+
+    Usage: L = MultipoleBatched.apply(M, com, plan)."""
+
+    @staticmethod
+    def forward(ctx, M, com, plan):
+        M = M.contiguous()
+        com = com.contiguous()
+        L = torch.empty((20, plan.T * 512), dtype=torch.float64, device=M.device)
+        plan.multipole_batched(M, com, L)
+        ctx.save_for_backward(M, com)
+        ctx.plan = plan
+        return L
+
+    @staticmethod
+    def backward(ctx, gL):
+        M, com = ctx.saved_tensors
+        gL = gL.contiguous()
+        gM = torch.empty_like(M)
+        gcom = torch.empty_like(com)
+        ctx.plan.multipole_backward(M, com, gL, gM, gcom)
+        return gM, gcom, None
+
+
+def multipole(M, com, plan):
+    """Differentiable batched multipole interaction (see MultipoleBatched)."""
+    return MultipoleBatched.apply(M, com, plan)

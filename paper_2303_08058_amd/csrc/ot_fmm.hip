@@ -1,0 +1,1154 @@
+// ot_fmm.hip -- MI355X (gfx950) FP64 fast-multipole cell-to-cell interaction
+// kernels behind the C ABI declared in include/ot_fmm.h.
+//
+// Method (paper Sec. 2.1: Octo-Tiger's gravity solver is an FMM on an octree
+// of 8^3 sub-grids; Sec. 2.2.1 / 2.3: a kernel works on one sub-grid plus its
+// ghost layers; Sec. 2.2.4: kernels of many sub-grids are aggregated into one
+// launch). For each target cell i and |alpha| <= 3:
+//   L_alpha(i) = sum_{j in S(i)} sum_{|beta|<=3-|alpha|} s_beta M_beta(j) G_{alpha+beta}(X_i - X_j)
+// with G = -1/|r|, s_beta = (-1)^{|beta|}/beta!, S(i) the opening-criterion
+// stencil (|j-i| > 4 and |floor(j/2) - floor(i/2)| <= 4) inside the 24^3 halo.
+//
+// Design (CDNA4):
+//  * One work-group per target sub-grid (batched: per work-list entry). The
+//    24^3 halo (2.54 MB of FP64 for moments + centres) cannot sit in the
+//    160 KB LDS, so it streams through LDS one source z-plane at a time
+//    (24 x 24 cells x 23 components = 106 KB), read from HBM with coalesced
+//    512-byte rows.
+//  * A wavefront = the 64 cells of one target z-plane (lane = x + 8 y). The
+//    stencil depends only on the target's parity; the parities differing in
+//    x or y are mirror images of each other (the criterion is invariant
+//    under j -> 23 - j), so every lane walks the same per-z-parity offset
+//    table (a list of (dy, dx-interval) rows per dz) with its own x/y sign.
+//    Offsets are wave-uniform: no masking, scalar-unit loop control, and one
+//    VALU add per offset for the LDS address. Bank mapping of the 8x8 lane
+//    pattern with 24-wide rows is conflict-free for ds_read_b64.
+//  * All arithmetic is FP64 VALU: per pair one rsqrt (v_rsq_f64 plus a
+//    third-order Newton correction), the derivatives of 1/r from the radial
+//    factors D_n = (-1)^{n+1} (2n-1)!! / r^{2n+1}, and the contraction
+//    (84 FMAs for the multipole). Source moments are pre-scaled by s_beta
+//    when staged, so the inner loop is FMAs only. There is no shared dense
+//    operand between pairs, so MFMA does not apply.
+//  * Missing neighbours are staged as zero moments at a far, finite centre:
+//    their terms are exact zeros, identical to dropping the pairs.
+//  * The adjoint is two gather passes with the same skeleton (no atomics):
+//    a source-role pass per store sub-grid (sources = the target cells that
+//    see it, carrying the weights) and a target-role pass per target.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ot_fmm.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(OT_FMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define OT_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Geometry constants
+// ---------------------------------------------------------------------------
+constexpr int kSub3 = 512;
+constexpr int kHalo = 24;
+constexpr int kPlane = kHalo * kHalo;   // 576 cells per halo z-plane
+constexpr int kHalo3 = kPlane * kHalo;  // 13824
+constexpr int kReach = 9;               // max |d_k| in the stencil
+constexpr int kMaxRows = 2 * (2 * kReach + 1) * (2 * kReach + 1);
+constexpr double kFar = 1.0e20;         // centre used for missing cells
+
+// ---------------------------------------------------------------------------
+// Multi-indices, graded lexicographic with x most significant
+// ---------------------------------------------------------------------------
+struct Exp3 {
+    int a, b, c;
+};
+
+__host__ __device__ constexpr int ncomp(int o) { return (o + 1) * (o + 2) * (o + 3) / 6; }
+
+__host__ __device__ constexpr Exp3 exp_of(int g)
+{
+    int k = 0;
+    for (int n = 0; n <= 8; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                if (k == g) return Exp3{a, b, n - a - b};
+                ++k;
+            }
+    return Exp3{-1, -1, -1};
+}
+
+__host__ __device__ constexpr int ord_of(int g)
+{
+    return exp_of(g).a + exp_of(g).b + exp_of(g).c;
+}
+
+__host__ __device__ constexpr int idx_of(int a, int b, int c)
+{
+    const int n = a + b + c;
+    int k = n > 0 ? ncomp(n - 1) : 0;
+    for (int ap = n; ap > a; --ap) k += n - ap + 1;
+    return k + (n - a) - b;
+}
+
+__host__ __device__ constexpr int sum_idx(int g, int h)
+{
+    return idx_of(exp_of(g).a + exp_of(h).a, exp_of(g).b + exp_of(h).b,
+                  exp_of(g).c + exp_of(h).c);
+}
+
+__host__ __device__ constexpr double factorial(int n) { return n <= 1 ? 1.0 : n * factorial(n - 1); }
+
+__host__ __device__ constexpr double inv_multi_factorial(int g)
+{
+    return 1.0 / (factorial(exp_of(g).a) * factorial(exp_of(g).b) * factorial(exp_of(g).c));
+}
+
+__host__ __device__ constexpr double parity_sign(int g) { return (ord_of(g) & 1) ? -1.0 : 1.0; }
+
+constexpr bool check_indices()
+{
+    for (int g = 0; g < 35; ++g)
+        if (idx_of(exp_of(g).a, exp_of(g).b, exp_of(g).c) != g) return false;
+    return ord_of(19) == 3 && ord_of(20) == 4 && sum_idx(1, 2) == 5 && sum_idx(4, 3) == 12;
+}
+static_assert(check_indices(), "multi-index tables");
+
+// Staging scale of the source components: forward sources carry
+// s_beta = (-1)^{|beta|}/beta!, adjoint sources carry (-1)^{|alpha|}.
+__constant__ double c_scale_fwd[20] = {
+    parity_sign(0) * inv_multi_factorial(0),   parity_sign(1) * inv_multi_factorial(1),
+    parity_sign(2) * inv_multi_factorial(2),   parity_sign(3) * inv_multi_factorial(3),
+    parity_sign(4) * inv_multi_factorial(4),   parity_sign(5) * inv_multi_factorial(5),
+    parity_sign(6) * inv_multi_factorial(6),   parity_sign(7) * inv_multi_factorial(7),
+    parity_sign(8) * inv_multi_factorial(8),   parity_sign(9) * inv_multi_factorial(9),
+    parity_sign(10) * inv_multi_factorial(10), parity_sign(11) * inv_multi_factorial(11),
+    parity_sign(12) * inv_multi_factorial(12), parity_sign(13) * inv_multi_factorial(13),
+    parity_sign(14) * inv_multi_factorial(14), parity_sign(15) * inv_multi_factorial(15),
+    parity_sign(16) * inv_multi_factorial(16), parity_sign(17) * inv_multi_factorial(17),
+    parity_sign(18) * inv_multi_factorial(18), parity_sign(19) * inv_multi_factorial(19)};
+__constant__ double c_scale_rev[20] = {
+    parity_sign(0),  parity_sign(1),  parity_sign(2),  parity_sign(3),  parity_sign(4),
+    parity_sign(5),  parity_sign(6),  parity_sign(7),  parity_sign(8),  parity_sign(9),
+    parity_sign(10), parity_sign(11), parity_sign(12), parity_sign(13), parity_sign(14),
+    parity_sign(15), parity_sign(16), parity_sign(17), parity_sign(18), parity_sign(19)};
+
+// ---------------------------------------------------------------------------
+// Stencil: for target parity (0, 0, pz), the offsets d = j - i grouped into
+// rows (dz, dy, [dx0, dx0 + n)). Built at compile time from the criterion.
+// Targets of x (y) parity 1 use the same rows with dx (dy) negated.
+// ---------------------------------------------------------------------------
+constexpr int floor_half(int v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+
+constexpr bool criterion(int ix, int iy, int iz, int jx, int jy, int jz)
+{
+    const int dx = jx - ix, dy = jy - iy, dz = jz - iz;
+    const int px = floor_half(jx) - floor_half(ix), py = floor_half(jy) - floor_half(iy),
+              pz = floor_half(jz) - floor_half(iz);
+    return dx * dx + dy * dy + dz * dz > 16 && px * px + py * py + pz * pz <= 16;
+}
+
+struct StencilTable {
+    uint32_t rows[2][kMaxRows];           // packed: dy | dx0 << 8 | n << 16
+    int range[2][2 * kReach + 1][3];      // per (pz, dz+9): first row, split row, end row
+    int count[2];                         // offsets per parity (1799)
+};
+
+constexpr uint32_t pack_row(int dy, int dx0, int n)
+{
+    return (uint32_t)(dy & 0xff) | ((uint32_t)(dx0 & 0xff) << 8) | ((uint32_t)n << 16);
+}
+
+constexpr StencilTable build_stencil()
+{
+    StencilTable t{};
+    for (int pz = 0; pz < 2; ++pz) {
+        const int ix = 8, iy = 8, iz = 8 + pz;
+        int nr = 0, total = 0;
+        for (int dz = -kReach; dz <= kReach; ++dz) {
+            const int first = nr;
+            int offs = 0;
+            for (int dy = -kReach; dy <= kReach; ++dy) {
+                int dx = -kReach;
+                while (dx <= kReach) {
+                    if (!criterion(ix, iy, iz, ix + dx, iy + dy, iz + dz)) {
+                        ++dx;
+                        continue;
+                    }
+                    int n = 0;
+                    while (dx + n <= kReach && criterion(ix, iy, iz, ix + dx + n, iy + dy, iz + dz))
+                        ++n;
+                    t.rows[pz][nr++] = pack_row(dy, dx, n);
+                    offs += n;
+                    dx += n;
+                }
+            }
+            // split point: first row at which the running count reaches half
+            int split = first, run = 0;
+            while (split < nr && 2 * run < offs) {
+                run += (int)(t.rows[pz][split] >> 16);
+                ++split;
+            }
+            if (split > first && 2 * run - offs > offs - 2 * (run - (int)(t.rows[pz][split - 1] >> 16)))
+                --split;
+            t.range[pz][dz + kReach][0] = first;
+            t.range[pz][dz + kReach][1] = split;
+            t.range[pz][dz + kReach][2] = nr;
+            total += offs;
+        }
+        t.count[pz] = total;
+    }
+    return t;
+}
+
+constexpr StencilTable kStencilHost = build_stencil();
+static_assert(kStencilHost.count[0] == 1799 && kStencilHost.count[1] == 1799, "stencil size");
+__constant__ StencilTable c_stencil = build_stencil();
+
+// Exact number of pairs between the 8^3 target cells and the neighbour block
+// at each slot, plus a check that the mirrored table reproduces the stencil
+// of every parity. Computed once on the host.
+struct SlotCounts {
+    int64_t pairs[27];
+    bool mirror_ok;
+};
+
+SlotCounts compute_slot_counts()
+{
+    SlotCounts sc{};
+    for (int slot = 0; slot < 27; ++slot) {
+        const int ox = 8 * (slot % 3), oy = 8 * ((slot / 3) % 3), oz = 8 * (slot / 9);
+        int64_t n = 0;
+        for (int i = 0; i < kSub3; ++i) {
+            const int ix = 8 + i % 8, iy = 8 + (i / 8) % 8, iz = 8 + i / 64;
+            for (int j = 0; j < kSub3; ++j)
+                n += criterion(ix, iy, iz, ox + j % 8, oy + (j / 8) % 8, oz + j / 64);
+        }
+        sc.pairs[slot] = n;
+    }
+    // every parity's brute-force stencil == mirrored rows of its z-parity
+    bool ok = true;
+    for (int p = 0; p < 8 && ok; ++p) {
+        const int px = p & 1, py = (p >> 1) & 1, pz = p >> 2;
+        const int ix = 8 + px, iy = 8 + py, iz = 8 + pz;
+        static bool mark[19][19][19];
+        std::memset(mark, 0, sizeof(mark));
+        int n_table = 0;
+        for (int dz = -kReach; dz <= kReach; ++dz) {
+            const int* rg = kStencilHost.range[pz][dz + kReach];
+            for (int r = rg[0]; r < rg[2]; ++r) {
+                const uint32_t w = kStencilHost.rows[pz][r];
+                const int dy = (int8_t)(w & 0xff), dx0 = (int8_t)((w >> 8) & 0xff), n = (int)(w >> 16);
+                for (int k = 0; k < n; ++k) {
+                    const int dx = (px ? -1 : 1) * (dx0 + k), dyy = (py ? -1 : 1) * dy;
+                    if (!criterion(ix, iy, iz, ix + dx, iy + dyy, iz + dz)) ok = false;
+                    mark[dz + 9][dyy + 9][dx + 9] = true;
+                    ++n_table;
+                }
+            }
+        }
+        int n_brute = 0;
+        for (int dz = -kReach; dz <= kReach; ++dz)
+            for (int dy = -kReach; dy <= kReach; ++dy)
+                for (int dx = -kReach; dx <= kReach; ++dx)
+                    if (criterion(ix, iy, iz, ix + dx, iy + dy, iz + dz)) {
+                        ++n_brute;
+                        if (!mark[dz + 9][dy + 9][dx + 9]) ok = false;
+                    }
+        if (n_brute != n_table) ok = false;
+    }
+    sc.mirror_ok = ok;
+    return sc;
+}
+
+const SlotCounts& slot_counts()
+{
+    static const SlotCounts sc = compute_slot_counts();
+    return sc;
+}
+
+// ---------------------------------------------------------------------------
+// Per-pair arithmetic
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_fp64(double a)
+{
+    // hardware estimate, then y (1 + e/2 + 3e^2/8) with e = 1 - a y^2
+    double y = __builtin_amdgcn_rsq(a);
+    const double e = __builtin_fma(-a * y, y, 1.0);
+    y = __builtin_fma(y * e, __builtin_fma(0.375, e, 0.5), y);
+    return y;
+}
+
+// G_gamma(r), |gamma| <= ORD (3 or 4), graded-lex order, from the radial
+// factors D0 = -1/r, D1 = 1/r^3, D2 = -3/r^5, D3 = 15/r^7, D4 = -105/r^9:
+//   G_a = r_a D1, G_ab = r_a r_b D2 + d_ab D1,
+//   G_abc = r_a r_b r_c D3 + (d_ab r_c + d_ac r_b + d_bc r_a) D2,
+//   G_abcd = r_a r_b r_c r_d D4 + (sum of 6 d r r) D3 + (sum of 3 d d) D2.
+template <int ORD>
+__device__ __forceinline__ void green(double x, double y, double z, double* G)
+{
+    const double r2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
+    const double ri = rsqrt_fp64(r2);
+    const double ri2 = ri * ri;
+    const double D1 = ri * ri2;
+    const double D2 = -3.0 * D1 * ri2;
+    const double D3 = -5.0 * D2 * ri2;
+    G[0] = -ri;
+    G[1] = x * D1;
+    G[2] = y * D1;
+    G[3] = z * D1;
+    const double xD2 = x * D2, yD2 = y * D2, zD2 = z * D2;
+    G[4] = __builtin_fma(x, xD2, D1);
+    G[5] = x * yD2;
+    G[6] = x * zD2;
+    G[7] = __builtin_fma(y, yD2, D1);
+    G[8] = y * zD2;
+    G[9] = __builtin_fma(z, zD2, D1);
+    const double xD3 = x * D3, yD3 = y * D3, zD3 = z * D3;
+    const double xx3 = x * xD3, xy3 = x * yD3, xz3 = x * zD3;
+    const double yy3 = y * yD3, yz3 = y * zD3, zz3 = z * zD3;
+    G[10] = __builtin_fma(x, xx3, 3.0 * xD2);  // xxx
+    G[11] = __builtin_fma(y, xx3, yD2);        // xxy
+    G[12] = __builtin_fma(z, xx3, zD2);        // xxz
+    G[13] = __builtin_fma(x, yy3, xD2);        // xyy
+    G[14] = z * xy3;                           // xyz
+    G[15] = __builtin_fma(x, zz3, xD2);        // xzz
+    G[16] = __builtin_fma(y, yy3, 3.0 * yD2);  // yyy
+    G[17] = __builtin_fma(z, yy3, zD2);        // yyz
+    G[18] = __builtin_fma(y, zz3, yD2);        // yzz
+    G[19] = __builtin_fma(z, zz3, 3.0 * zD2);  // zzz
+    if constexpr (ORD >= 4) {
+        const double D4 = -7.0 * D3 * ri2;
+        const double xD4 = x * D4, yD4 = y * D4, zD4 = z * D4;
+        const double xx4 = x * xD4, xy4 = x * yD4, xz4 = x * zD4;
+        const double yy4 = y * yD4, yz4 = y * zD4, zz4 = z * zD4;
+        G[20] = __builtin_fma(x * x, xx4, __builtin_fma(6.0, xx3, 3.0 * D2));            // xxxx
+        G[21] = __builtin_fma(x * y, xx4, 3.0 * xy3);                                   // xxxy
+        G[22] = __builtin_fma(x * z, xx4, 3.0 * xz3);                                   // xxxz
+        G[23] = __builtin_fma(y * y, xx4, __builtin_fma(1.0, xx3 + yy3, D2));           // xxyy
+        G[24] = __builtin_fma(y * z, xx4, yz3);                                         // xxyz
+        G[25] = __builtin_fma(z * z, xx4, __builtin_fma(1.0, xx3 + zz3, D2));           // xxzz
+        G[26] = __builtin_fma(x * y, yy4, 3.0 * xy3);                                   // xyyy
+        G[27] = __builtin_fma(x * z, yy4, xz3);                                         // xyyz
+        G[28] = __builtin_fma(x * y, zz4, xy3);                                         // xyzz
+        G[29] = __builtin_fma(x * z, zz4, 3.0 * xz3);                                   // xzzz
+        G[30] = __builtin_fma(y * y, yy4, __builtin_fma(6.0, yy3, 3.0 * D2));           // yyyy
+        G[31] = __builtin_fma(y * z, yy4, 3.0 * yz3);                                   // yyyz
+        G[32] = __builtin_fma(z * z, yy4, __builtin_fma(1.0, yy3 + zz3, D2));           // yyzz
+        G[33] = __builtin_fma(y * z, zz4, 3.0 * yz3);                                   // yzzz
+        G[34] = __builtin_fma(z * z, zz4, __builtin_fma(6.0, zz3, 3.0 * D2));           // zzzz
+        (void)xD4;
+        (void)yD4;
+        (void)zD4;
+        (void)xy4;
+        (void)xz4;
+        (void)yz4;
+    }
+}
+
+// L[A] += sum_{B: |A|+|B| <= 3} q[B] G[A+B]      (forward contraction, 84 FMAs)
+template <int A, int B>
+__device__ __forceinline__ void term_fwd(double* L, const double* q, const double* G)
+{
+    if constexpr (ord_of(A) + ord_of(B) <= 3) {
+        constexpr int S = sum_idx(A, B);
+        L[A] = __builtin_fma(q[B], G[S], L[A]);
+    }
+}
+template <int A, int... B>
+__device__ __forceinline__ void row_fwd(double* L, const double* q, const double* G,
+                                        std::integer_sequence<int, B...>)
+{
+    (term_fwd<A, B>(L, q, G), ...);
+}
+template <int... A>
+__device__ __forceinline__ void contract_fwd(double* L, const double* q, const double* G,
+                                             std::integer_sequence<int, A...>)
+{
+    (row_fwd<A>(L, q, G, std::make_integer_sequence<int, 20>{}), ...);
+}
+
+// E[C-1] += sum_{A: |A| + |C| = 4} q[A] G[A+C]   for 1 <= |C| <= 4 (111 FMAs)
+template <int C, int A>
+__device__ __forceinline__ void term_e(double* E, const double* q, const double* G)
+{
+    if constexpr (ord_of(A) + ord_of(C) == 4) {
+        constexpr int S = sum_idx(A, C);
+        E[C - 1] = __builtin_fma(q[A], G[S], E[C - 1]);
+    }
+}
+template <int C, int... A>
+__device__ __forceinline__ void row_e(double* E, const double* q, const double* G,
+                                      std::integer_sequence<int, A...>)
+{
+    (term_e<C + 1, A>(E, q, G), ...);
+}
+template <int... C>
+__device__ __forceinline__ void contract_e(double* E, const double* q, const double* G,
+                                           std::integer_sequence<int, C...>)
+{
+    (row_e<C>(E, q, G, std::make_integer_sequence<int, 20>{}), ...);
+}
+
+// Adjoint epilogue: with C_g = F_g + E_g (1 <= |g| <= 3) and C_g = E_g
+// (|g| = 4), the position gradient is gX_k = sum_a c_a C_{a+e_k}, where c_a is
+// the target's weight w_a (target role) or M_a / a! (source role).
+template <int A, int K>
+__device__ __forceinline__ double c_term(const double* F, const double* E)
+{
+    constexpr int g = sum_idx(A, K);
+    if constexpr (g < 20)
+        return F[g] + E[g - 1];
+    else
+        return E[g - 1];
+}
+template <int... A>
+__device__ __forceinline__ void grad_x(const double* c, const double* F, const double* E,
+                                       double* gx, std::integer_sequence<int, A...>)
+{
+    ((gx[0] = __builtin_fma(c[A], c_term<A, 1>(F, E), gx[0]),
+      gx[1] = __builtin_fma(c[A], c_term<A, 2>(F, E), gx[1]),
+      gx[2] = __builtin_fma(c[A], c_term<A, 3>(F, E), gx[2])),
+     ...);
+}
+template <int A>
+__device__ __forceinline__ double inv_fact_c()
+{
+    constexpr double f = inv_multi_factorial(A);
+    return f;
+}
+template <int... A>
+__device__ __forceinline__ void scale_inv_fact(double* c, std::integer_sequence<int, A...>)
+{
+    ((c[A] *= inv_fact_c<A>()), ...);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel
+// ---------------------------------------------------------------------------
+enum Mode : int {
+    MODE_MONO_HALO = 0,  // single block, mass only -> L
+    MODE_FWD_HALO = 1,   // single block, moments -> L
+    MODE_FWD_STORE = 2,  // batched forward -> L
+    MODE_B2_STORE = 3,   // adjoint, source role per store sub-grid -> gM, gX (overwrite)
+    MODE_B1_STORE = 4    // adjoint, target role per target -> gX (accumulate)
+};
+
+struct KParams {
+    const double* mom;   // source moments / masses / weights, [ncomp][mom_stride]
+    const double* pos;   // centres of mass, [3][pos_stride] (halo or store)
+    long mom_stride;
+    long pos_stride;
+    const int4* rel;       // [owners][27]: {moment block, position block, packed shift, 0}
+    const int* own_blk;    // owner -> store block of its own cells (NULL: identity)
+    const int* order;      // work-group -> owner (NULL: identity)
+    const double* aux;     // epilogue input: gL (B1) or M (B2), [20][aux_stride]
+    long aux_stride;
+    double* out0;          // L, or gM (B2), or gX (B1)
+    double* out1;          // gX (B2)
+    long out_stride;
+    const int* out_blk;    // owner -> output block (NULL: identity)
+    double period[3];
+};
+
+template <int MODE>
+struct ModeTraits {
+    static constexpr bool halo = (MODE == MODE_MONO_HALO || MODE == MODE_FWD_HALO);
+    static constexpr int nq = (MODE == MODE_MONO_HALO) ? 1 : 20;  // staged source moments
+    static constexpr int nc = nq + 3;                              // + centre of mass
+    static constexpr bool adjoint = (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE);
+    static constexpr int nacc = adjoint ? 54 : 20;
+};
+
+template <int MODE, int NW>
+constexpr int lds_doubles()
+{
+    constexpr int plane = ModeTraits<MODE>::nc * kPlane;
+    constexpr int merge = (NW == 16) ? 20 * kSub3 : 0;
+    return plane > merge ? plane : merge;
+}
+
+// Stage halo z-plane zs of the owner's neighbourhood into LDS as
+// lds[c][y * 24 + x]: components 0..nq-1 scaled sources, nq..nq+2 centres.
+template <int MODE, int NW>
+__device__ __forceinline__ void stage_plane(const KParams& p, int owner, int zs, double* lds)
+{
+    using T = ModeTraits<MODE>;
+    constexpr int NT = NW * 64;
+    const int tid = threadIdx.x;
+    if constexpr (T::halo) {
+        for (int e = tid; e < T::nc * kPlane; e += NT) {
+            const int c = e / kPlane;
+            const int i = e - c * kPlane;
+            double v;
+            if (c < T::nq)
+                v = p.mom[(long)c * kHalo3 + zs * kPlane + i] * c_scale_fwd[c];
+            else
+                v = p.pos[(long)(c - T::nq) * kHalo3 + zs * kPlane + i];
+            lds[e] = v;
+        }
+    } else {
+        const int bz = zs >> 3, lz = zs & 7;
+        const int4* rel = p.rel + (long)owner * 27 + 9 * bz;
+        for (int e = tid; e < T::nc * kPlane; e += NT) {
+            const int c = e / kPlane;
+            const int rem = e - c * kPlane;
+            const int bxy = rem >> 6, l = rem & 63;
+            const int by = bxy / 3, bx = bxy - 3 * by;
+            const int4 r = rel[bxy];
+            const long lidx = l + 64 * lz;
+            double v;
+            if (c < T::nq) {
+                const double s = (MODE == MODE_B2_STORE) ? c_scale_rev[c] : c_scale_fwd[c];
+                v = r.x >= 0 ? p.mom[(long)c * p.mom_stride + (long)r.x * kSub3 + lidx] * s : 0.0;
+            } else {
+                const int k = c - T::nq;
+                if (r.x >= 0) {
+                    const int sh = (int)(int8_t)((r.z >> (8 * k)) & 0xff);
+                    v = p.pos[(long)k * p.pos_stride + (long)r.y * kSub3 + lidx] +
+                        (double)sh * p.period[k];
+                } else {
+                    v = kFar;
+                }
+            }
+            lds[c * kPlane + (by * 8 + (l >> 3)) * kHalo + bx * 8 + (l & 7)] = v;
+        }
+    }
+}
+
+template <int MODE, int NW>
+__global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
+{
+    using T = ModeTraits<MODE>;
+    static_assert(NW == 8 || NW == 16, "8 or 16 wavefronts");
+    static_assert(!(T::adjoint && NW != 8), "adjoint passes use 8 wavefronts");
+    __shared__ double lds[lds_doubles<MODE, NW>()];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int owner = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
+    const int zt = (NW == 16) ? (wave >> 1) : wave;
+    const int half = (NW == 16) ? (wave & 1) : 0;
+    const int xt = lane & 7, yt = lane >> 3;
+    const int pz = zt & 1;
+    const int cell = xt + 8 * yt + 64 * zt;
+    const int sgx = (xt & 1) ? -1 : 1;
+    const int sgy = (yt & 1) ? -1 : 1;
+
+    double xi, yi, zi;
+    if constexpr (T::halo) {
+        const int h = (8 + xt) + kHalo * (8 + yt) + kPlane * (8 + zt);
+        xi = p.pos[h];
+        yi = p.pos[kHalo3 + h];
+        zi = p.pos[2 * kHalo3 + h];
+    } else {
+        const long b = p.own_blk ? p.own_blk[owner] : owner;
+        const long o = b * kSub3 + cell;
+        xi = p.pos[o];
+        yi = p.pos[p.pos_stride + o];
+        zi = p.pos[2 * p.pos_stride + o];
+    }
+
+    double acc[T::nacc];
+#pragma unroll
+    for (int a = 0; a < T::nacc; ++a) acc[a] = 0.0;
+
+    const int lane_base = (8 + yt) * kHalo + 8 + xt;
+    const int step_y = sgy * kHalo;
+
+    for (int zs = 0; zs < kHalo; ++zs) {
+        __syncthreads();
+        stage_plane<MODE, NW>(p, owner, zs, lds);
+        __syncthreads();
+        const int dz = zs - (8 + zt);
+        if (dz < -kReach || dz > kReach) continue;
+        const int* rg = c_stencil.range[pz][dz + kReach];
+        int r0 = rg[0], r1 = rg[2];
+        if (NW == 16) {
+            if (half == 0)
+                r1 = rg[1];
+            else
+                r0 = rg[1];
+        }
+        for (int r = r0; r < r1; ++r) {
+            const uint32_t w = c_stencil.rows[pz][r];
+            const int dy = (int)(int8_t)(w & 0xff);
+            const int dx0 = (int)(int8_t)((w >> 8) & 0xff);
+            const int n = (int)(w >> 16);
+            int idx = lane_base + dy * step_y + dx0 * sgx;
+            for (int k = 0; k < n; ++k, idx += sgx) {
+                const double rx = xi - lds[(T::nq + 0) * kPlane + idx];
+                const double ry = yi - lds[(T::nq + 1) * kPlane + idx];
+                const double rz = zi - lds[(T::nq + 2) * kPlane + idx];
+                double q[T::nq];
+#pragma unroll
+                for (int c = 0; c < T::nq; ++c) q[c] = lds[c * kPlane + idx];
+                if constexpr (MODE == MODE_MONO_HALO) {
+                    double G[20];
+                    green<3>(rx, ry, rz, G);
+#pragma unroll
+                    for (int a = 0; a < 20; ++a) acc[a] = __builtin_fma(q[0], G[a], acc[a]);
+                } else if constexpr (!T::adjoint) {
+                    double G[20];
+                    green<3>(rx, ry, rz, G);
+                    contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
+                } else {
+                    double G[35];
+                    green<4>(rx, ry, rz, G);
+                    contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
+                    contract_e(acc + 20, q, G, std::make_integer_sequence<int, 34>{});
+                }
+            }
+        }
+    }
+
+    // ---------------- epilogues ----------------
+    if constexpr (!T::adjoint) {
+        if constexpr (NW == 16) {
+            __syncthreads();
+            if (half == 1) {
+#pragma unroll
+                for (int a = 0; a < 20; ++a) lds[a * kSub3 + cell] = acc[a];
+            }
+            __syncthreads();
+            if (half == 1) return;
+#pragma unroll
+            for (int a = 0; a < 20; ++a) acc[a] += lds[a * kSub3 + cell];
+        }
+        if constexpr (T::halo) {
+#pragma unroll
+            for (int a = 0; a < 20; ++a) p.out0[a * kSub3 + cell] = acc[a];
+        } else {
+            const long b = p.out_blk ? p.out_blk[owner] : owner;
+#pragma unroll
+            for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + b * kSub3 + cell] = acc[a];
+        }
+    } else {
+        const double* F = acc;
+        const double* E = acc + 20;
+        const long ab = (long)owner * kSub3 + cell;
+        double c[20];
+#pragma unroll
+        for (int a = 0; a < 20; ++a) c[a] = p.aux[a * p.aux_stride + ab];
+        if constexpr (MODE == MODE_B2_STORE)
+            scale_inv_fact(c, std::make_integer_sequence<int, 20>{});  // M_b / b!
+        double gx[3] = {0.0, 0.0, 0.0};
+        grad_x(c, F, E, gx, std::make_integer_sequence<int, 20>{});
+        const long b = p.out_blk ? p.out_blk[owner] : owner;
+        const long ob = b * kSub3 + cell;
+        if constexpr (MODE == MODE_B2_STORE) {
+            double gm[20];
+#pragma unroll
+            for (int a = 0; a < 20; ++a) gm[a] = F[a];
+            scale_inv_fact(gm, std::make_integer_sequence<int, 20>{});  // F_b / b!
+#pragma unroll
+            for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = gm[a];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) p.out1[k * p.out_stride + ob] = gx[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) p.out0[k * p.out_stride + ob] += gx[k];
+        }
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mutex;
+int g_dev_state[kMaxDevices];  // 0 unknown, 1 gfx950 ready, -1 unsupported
+
+int ensure_device()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(OT_FMM_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (g_dev_state[dev] == 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        if (ok && !slot_counts().mirror_ok) {
+            g_dev_state[dev] = -1;
+            return fail(OT_FMM_EUNSUPPORTED, "stencil mirror check failed");
+        }
+        g_dev_state[dev] = ok ? 1 : -1;
+    }
+    if (g_dev_state[dev] < 0) return fail(OT_FMM_EUNSUPPORTED, "current device is not gfx950");
+    return OT_FMM_OK;
+}
+
+bool aligned8(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+template <int MODE, int NW>
+int launch(const KParams& kp, int nblocks, hipStream_t stream)
+{
+    if (nblocks <= 0) return OT_FMM_OK;
+    hipLaunchKernelGGL((k_interact<MODE, NW>), dim3(nblocks), dim3(NW * 64), 0, stream, kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return OT_FMM_OK;
+}
+
+int pick_fwd(int sched, int tuned)
+{
+    if (sched == OT_FMM_SCHED_AUTO) sched = tuned ? tuned : OT_FMM_SCHED_W16;
+    return sched;
+}
+
+}  // namespace
+
+struct ot_fmm_plan_s {
+    int device = 0;
+    int32_t S = 0, T = 0;
+    bool has_shift = false;
+    double period[3] = {0.0, 0.0, 0.0};
+    int64_t pairs = 0;
+    int4* d_fwd_rel = nullptr;  // [T][27]
+    int4* d_rev_rel = nullptr;  // [S][27]
+    int* d_tgt = nullptr;       // [T]
+    int* d_fwd_order = nullptr; // [T]
+    int* d_rev_order = nullptr; // [S]
+    int tuned_fwd = 0, tuned_bwd = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, int sched,
+                hipStream_t stream)
+{
+    KParams kp{};
+    kp.mom = M;
+    kp.pos = com;
+    kp.mom_stride = (long)plan->S * kSub3;
+    kp.pos_stride = (long)plan->S * kSub3;
+    kp.rel = plan->d_fwd_rel;
+    kp.own_blk = plan->d_tgt;
+    kp.order = plan->d_fwd_order;
+    kp.out0 = L;
+    kp.out_stride = (long)plan->T * kSub3;
+    kp.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
+    sched = pick_fwd(sched, plan->tuned_fwd);
+    if (sched == OT_FMM_SCHED_W8) return launch<MODE_FWD_STORE, 8>(kp, plan->T, stream);
+    if (sched == OT_FMM_SCHED_W16) return launch<MODE_FWD_STORE, 16>(kp, plan->T, stream);
+    return fail(OT_FMM_EINVAL, "unknown forward schedule");
+}
+
+int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
+                double* gM, double* gcom, int sched, hipStream_t stream)
+{
+    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_bwd ? plan->tuned_bwd : OT_FMM_SCHED_W8;
+    if (sched != OT_FMM_SCHED_W8) return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    const long NS = (long)plan->S * kSub3, NT = (long)plan->T * kSub3;
+    // source role: owners are store sub-grids, sources the target cells that see them
+    KParams b2{};
+    b2.mom = gL;
+    b2.mom_stride = NT;
+    b2.pos = com;
+    b2.pos_stride = NS;
+    b2.rel = plan->d_rev_rel;
+    b2.own_blk = nullptr;
+    b2.order = plan->d_rev_order;
+    b2.aux = M;
+    b2.aux_stride = NS;
+    b2.out0 = gM;
+    b2.out1 = gcom;
+    b2.out_stride = NS;
+    b2.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) b2.period[k] = plan->period[k];
+    int rc = launch<MODE_B2_STORE, 8>(b2, plan->S, stream);
+    if (rc) return rc;
+    // target role: owners are targets, sources their neighbours' cells
+    KParams b1{};
+    b1.mom = M;
+    b1.mom_stride = NS;
+    b1.pos = com;
+    b1.pos_stride = NS;
+    b1.rel = plan->d_fwd_rel;
+    b1.own_blk = plan->d_tgt;
+    b1.order = plan->d_fwd_order;
+    b1.aux = gL;
+    b1.aux_stride = NT;
+    b1.out0 = gcom;
+    b1.out_stride = NS;
+    b1.out_blk = plan->d_tgt;
+    for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
+    return launch<MODE_B1_STORE, 8>(b1, plan->T, stream);
+}
+
+int check_plan(ot_fmm_plan plan)
+{
+    if (!plan) return fail(OT_FMM_EINVAL, "null plan");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != plan->device) return fail(OT_FMM_EINVAL, "plan belongs to another device");
+    return OT_FMM_OK;
+}
+
+void free_plan_memory(ot_fmm_plan p)
+{
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    (void)hipFree(p->d_fwd_rel);
+    (void)hipFree(p->d_rev_rel);
+    (void)hipFree(p->d_tgt);
+    (void)hipFree(p->d_fwd_order);
+    (void)hipFree(p->d_rev_order);
+}
+
+template <class Tp>
+int upload(Tp** dst, const std::vector<Tp>& src)
+{
+    *dst = nullptr;
+    if (src.empty()) return OT_FMM_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(Tp));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        return fail(OT_FMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    e = hipMemcpy(*dst, src.data(), src.size() * sizeof(Tp), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    return OT_FMM_OK;
+}
+
+// Work order: longest work first (a greedy longest-processing-time list for
+// the hardware dispatcher), ties kept in store order for locality.
+std::vector<int> lpt_order(const std::vector<int64_t>& work)
+{
+    std::vector<int> idx(work.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[a] > work[b]; });
+    return idx;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int ot_fmm_version(void) { return OT_FMM_VERSION; }
+
+const char* ot_fmm_strerror(int code)
+{
+    switch (code) {
+    case OT_FMM_OK: return "ok";
+    case OT_FMM_EINVAL: return "invalid argument";
+    case OT_FMM_EHIP: return "HIP runtime error";
+    case OT_FMM_ENOMEM: return "device allocation failed";
+    case OT_FMM_EUNSUPPORTED: return "unsupported device";
+    default: return "unknown error";
+    }
+}
+
+const char* ot_fmm_last_error(void) { return g_last_error.c_str(); }
+
+int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stream)
+{
+    g_last_error.clear();
+    if (!aligned8(mass) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    int rc = ensure_device();
+    if (rc) return rc;
+    KParams kp{};
+    kp.mom = mass;
+    kp.pos = com;
+    kp.out0 = L;
+    return launch<MODE_MONO_HALO, 16>(kp, 1, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream)
+{
+    g_last_error.clear();
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    int rc = ensure_device();
+    if (rc) return rc;
+    KParams kp{};
+    kp.mom = M;
+    kp.pos = com;
+    kp.out0 = L;
+    return launch<MODE_FWD_HALO, 16>(kp, 1, (hipStream_t)stream);
+}
+
+int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr,
+                       const int8_t* shift, const double* period, ot_fmm_plan* out)
+{
+    g_last_error.clear();
+    if (!out) return fail(OT_FMM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (S <= 0 || T <= 0) return fail(OT_FMM_EINVAL, "S and T must be positive");
+    if ((int64_t)S * kSub3 * 20 > ((int64_t)1 << 40) || (int64_t)T * 27 > ((int64_t)1 << 31))
+        return fail(OT_FMM_EINVAL, "descriptor too large");
+    if (!tgt || !nbr) return fail(OT_FMM_EINVAL, "null tgt or nbr");
+    if (shift && !period) return fail(OT_FMM_EINVAL, "shift given without period");
+    std::vector<char> seen(S, 0);
+    for (int t = 0; t < T; ++t) {
+        if (tgt[t] < 0 || tgt[t] >= S) return fail(OT_FMM_EINVAL, "tgt out of range");
+        if (seen[tgt[t]]) return fail(OT_FMM_EINVAL, "tgt entries must be distinct");
+        seen[tgt[t]] = 1;
+        for (int s = 0; s < 27; ++s) {
+            const int32_t v = nbr[(int64_t)t * 27 + s];
+            if (v < -1 || v >= S) return fail(OT_FMM_EINVAL, "nbr out of range");
+        }
+        if (nbr[(int64_t)t * 27 + 13] != tgt[t]) return fail(OT_FMM_EINVAL, "nbr[t][13] != tgt[t]");
+    }
+    if (period)
+        for (int k = 0; k < 3; ++k)
+            if (!(period[k] == period[k]) || period[k] > 1e15 || period[k] < -1e15)
+                return fail(OT_FMM_EINVAL, "period must be finite");
+    const SlotCounts& sc = slot_counts();
+    std::vector<int4> fwd((size_t)T * 27), rev((size_t)S * 27);
+    for (auto& r : rev) r = make_int4(-1, -1, 0, 0);
+    std::vector<int64_t> fwd_work(T, 0), rev_work(S, 0);
+    int64_t pairs = 0;
+    for (int t = 0; t < T; ++t)
+        for (int s = 0; s < 27; ++s) {
+            const int32_t b = nbr[(int64_t)t * 27 + s];
+            int packed = 0, packed_neg = 0;
+            if (shift) {
+                for (int k = 0; k < 3; ++k) {
+                    const int v = shift[((int64_t)t * 27 + s) * 3 + k];
+                    packed |= (v & 0xff) << (8 * k);
+                    packed_neg |= ((-v) & 0xff) << (8 * k);
+                }
+            }
+            fwd[(size_t)t * 27 + s] = make_int4(b, b, packed, 0);
+            if (b < 0) continue;
+            if (shift)
+                for (int k = 0; k < 3; ++k)
+                    if (shift[((int64_t)t * 27 + s) * 3 + k] == -128)
+                        return fail(OT_FMM_EINVAL, "shift of -128 cannot be negated");
+            const size_t ri = (size_t)b * 27 + (26 - s);
+            if (rev[ri].x >= 0)
+                return fail(OT_FMM_EINVAL, "two targets claim the same (source, slot) relation");
+            rev[ri] = make_int4(t, tgt[t], packed_neg, 0);
+            fwd_work[t] += sc.pairs[s];
+            rev_work[b] += sc.pairs[s];
+            pairs += sc.pairs[s];
+        }
+    std::vector<int> tg(tgt, tgt + T);
+    std::vector<int> fo = lpt_order(fwd_work), ro = lpt_order(rev_work);
+    int rc = ensure_device();
+    if (rc) return rc;
+
+    ot_fmm_plan p = new (std::nothrow) ot_fmm_plan_s();
+    if (!p) return fail(OT_FMM_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDevice");
+    }
+    p->S = S;
+    p->T = T;
+    p->has_shift = shift != nullptr;
+    if (period)
+        for (int k = 0; k < 3; ++k) p->period[k] = period[k];
+    p->pairs = pairs;
+    if ((rc = upload(&p->d_fwd_rel, fwd)) || (rc = upload(&p->d_rev_rel, rev)) ||
+        (rc = upload(&p->d_tgt, tg)) || (rc = upload(&p->d_fwd_order, fo)) ||
+        (rc = upload(&p->d_rev_order, ro))) {
+        free_plan_memory(p);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_plan_destroy(ot_fmm_plan plan)
+{
+    g_last_error.clear();
+    if (!plan) return OT_FMM_OK;
+    free_plan_memory(plan);
+    delete plan;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs)
+{
+    g_last_error.clear();
+    if (!plan || !pairs) return fail(OT_FMM_EINVAL, "null argument");
+    *pairs = plan->pairs;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                             int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (sched < 0 || sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
+    return fwd_batched(plan, M, com, L, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* com,
+                              const double* gL, double* gM, double* gcom, int sched,
+                              void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned8(M) || !aligned8(com) || !aligned8(gL) || !aligned8(gM) || !aligned8(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (gM == M || gM == gL || gcom == com || (const double*)gcom == gL || (const double*)gM == com)
+        return fail(OT_FMM_EINVAL, "outputs alias inputs");
+    if (sched != OT_FMM_SCHED_AUTO && sched != OT_FMM_SCHED_W8)
+        return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    return bwd_batched(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                    const double* gL, double* gM, double* gcom, void* stream, int* fwd_sched,
+                    int* bwd_sched)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    const bool with_bwd = gL || gM || gcom;
+    if (with_bwd && (!aligned8(gL) || !aligned8(gM) || !aligned8(gcom)))
+        return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    OT_HIP(hipEventCreate(&e0));
+    OT_HIP(hipEventCreate(&e1));
+    auto time_it = [&](auto&& fn, float* ms) -> int {
+        int r = fn();  // warm-up
+        if (r) return r;
+        OT_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < 3; ++i)
+            if ((r = fn())) return r;
+        OT_HIP(hipEventRecord(e1, s));
+        OT_HIP(hipEventSynchronize(e1));
+        OT_HIP(hipEventElapsedTime(ms, e0, e1));
+        return OT_FMM_OK;
+    };
+    int best_f = OT_FMM_SCHED_W16;
+    float best_ms = 3.0e38f;
+    for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16}) {
+        float ms = 0.0f;
+        rc = time_it([&] { return fwd_batched(plan, M, com, L, cand, s); }, &ms);
+        if (rc) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_f = cand;
+        }
+    }
+    int best_b = OT_FMM_SCHED_W8;
+    if (!rc && with_bwd) {
+        float ms = 0.0f;
+        rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, OT_FMM_SCHED_W8, s); }, &ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    plan->tuned_fwd = best_f;
+    plan->tuned_bwd = best_b;
+    if (fwd_sched) *fwd_sched = best_f;
+    if (bwd_sched) *bwd_sched = best_b;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                             const double* gL, double* gM, double* gcom, int fwd_sched,
+                             int bwd_sched)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    const bool with_bwd = gL || gM || gcom;
+    if (with_bwd && (!aligned8(gL) || !aligned8(gM) || !aligned8(gcom)))
+        return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
+    if (fwd_sched < 0 || fwd_sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
+    if (with_bwd && bwd_sched != OT_FMM_SCHED_AUTO && bwd_sched != OT_FMM_SCHED_W8)
+        return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    hipStream_t cs;
+    OT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = fwd_batched(plan, M, com, L, fwd_sched, cs);
+    if (!rc && with_bwd) rc = bwd_batched(plan, M, com, gL, gM, gcom, bwd_sched, cs);
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->graph = g;
+    plan->graph_exec = ex;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!plan->graph_exec) return fail(OT_FMM_EINVAL, "no step graph captured");
+    OT_HIP(hipGraphLaunch(plan->graph_exec, (hipStream_t)stream));
+    return OT_FMM_OK;
+}
+
+}  // extern "C"
