@@ -1,0 +1,322 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched FP64 FMM interaction kernels on one MI355X.
+
+Workload (default): 32^3 = 32768 sub-grids (256^3 = 16.8M cells) of a
+synthetic two-blob binary-star field (blob widths in {2h, 4h}, mass ratio
+drawn from U[0.3, 1.0]), periodic, 20% of the sub-grids missing 1..9
+neighbours. A step is the whole hot path over that batch: the batched
+multipole forward and its adjoint (source-role and target-role passes),
+replayed as one captured hipGraph. Inputs are resident in HBM before the
+timed region.
+
+Metric: FP64 cell-pair interactions per second of forward+backward; the pair
+count is exact (from the neighbour table). Also reported: the roofline of the
+dominant kernel (algorithmic FLOPs per launch / mean launch time, measured
+with HIP events on the launch stream), forward-only throughput, the batched
+launch against per-sub-grid launches of the single-block kernel on the
+4096-sub-grid forward workload (1, 8 and 32 streams), and the CPU oracle on a
+bounded sample of the same workload.
+
+Progress goes to stderr; stdout gets one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("FP64 cell-pair interactions/s (fwd, fwd+bwd): batched vs per-subgrid launch, "
+          "% FP64 peak")
+PEAK_FP64_TFLOPS = 78.6  # 256 CUs x 128 FP64 FLOP/clk x 2.4 GHz
+
+# Algorithmic FP64 operations per cell pair (FMA = 2, rsqrt = 1), counted from
+# the formulas the kernels evaluate:
+#   derivatives of 1/r to order 3 (incl. r = X_i - X_j): 61; to order 4: 121
+#   forward contraction: 84 FMA; adjoint source pass: 84 + 111 FMA;
+#   adjoint target pass: 64 + 111 FMA
+FLOP_PER_PAIR = {
+    "forward": 61 + 2 * 84,                # 229
+    "adjoint_source": 121 + 2 * (84 + 111),  # 511
+    "adjoint_target": 121 + 2 * (64 + 111),  # 471
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32, help="sub-grids per axis (32: 256^3 cells)")
+    ap.add_argument("--per-subgrid-n", type=int, default=16,
+                    help="sub-grids per axis of the batched-vs-per-sub-grid comparison (0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="approximate CPU time of the oracle baseline (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the kernels shard by sub-grid; "
+              "multi-GPU runs are not part of it). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2303_08058_amd as ot
+    import synthetic
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    def d(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    # ------------------------------------------------------------------ inputs
+    t0 = time.time()
+    batch, M, X = synthetic.config5(args.n)
+    log("inputs: %d sub-grids generated in %.1f s" % (batch["S"], time.time() - t0))
+    plan = ot.Plan.from_batch(batch)
+    pairs = plan.pairs()
+    w = synthetic.weights(batch["T"], 2005)
+    Md, Xd, wd = d(M), d(X), d(w)
+    NS, NT = batch["S"] * 512, batch["T"] * 512
+    L = torch.empty((20, NT), dtype=torch.float64, device=dev)
+    gM = torch.empty((20, NS), dtype=torch.float64, device=dev)
+    gX = torch.empty((3, NS), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    log("plan: %d targets, %d pairs" % (batch["T"], pairs))
+
+    fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
+    log("autotuned schedules: forward %d, backward %d" % (fs, bs))
+    plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
+
+    # ------------------------------------------------------------ timed steps
+    for _ in range(args.warmup):
+        plan.step_graph_launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        plan.step_graph_launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    log("graph step: %.2f ms (wall %.2f ms)" % (ms_per_step, wall * 1e3 / args.steps))
+
+    # per-kernel durations: the same step as direct launches, HIP events on the
+    # launch stream around every kernel
+    plan.set_timing(True)
+    plan.kernel_times()
+    for i in range(args.steps):
+        plan.multipole_batched(Md, Xd, L, sched=fs)
+        plan.multipole_backward(Md, Xd, wd, gM, gX, sched=bs)
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    kernels = {}
+    for k, (ms, n) in kt.items():
+        mean = ms / max(n, 1)
+        fl = pairs * FLOP_PER_PAIR[k]
+        kernels[k] = {"mean_ms": round(mean, 4), "launches": n,
+                      "tflops": round(fl / (mean * 1e-3) / 1e12, 3),
+                      "flop_per_pair": FLOP_PER_PAIR[k]}
+        log("kernel %-15s %.3f ms  %.2f TFLOP/s" % (k, mean, kernels[k]["tflops"]))
+    dom = max(kernels, key=lambda k: kernels[k]["mean_ms"])
+    achieved = kernels[dom]["tflops"]
+    fwd_pairs_s = pairs / (kernels["forward"]["mean_ms"] * 1e-3)
+    sum_ms = sum(v["mean_ms"] for v in kernels.values())
+    fwdbwd_flops = pairs * sum(FLOP_PER_PAIR.values()) / (ms_per_step * 1e-3) / 1e12
+
+    # copy of known size, for scaling HBM counters (not part of the step)
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # --------------------------------------- batched vs per-sub-grid launches
+    per_sub = None
+    if args.per_subgrid_n > 0:
+        per_sub = per_subgrid_comparison(args.per_subgrid_n, ot, synthetic, np, torch, dev)
+
+    # ----------------------------------------------------------- CPU oracle
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(batch, M, X, w, args.cpu_seconds, np)
+
+    out = {
+        "metric": METRIC,
+        "value": pairs / (ms_per_step * 1e-3),
+        "unit": "cell-pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched multipole forward+adjoint, %d^3 sub-grids (%d^3 cells), "
+                        "periodic, 20%% of sub-grids missing 1-9 neighbours, hipGraph step"
+                        % (args.n, 8 * args.n),
+            "subgrids": batch["S"], "cells": batch["S"] * 512, "pairs": pairs,
+            "field": batch["field"], "schedules": {"forward": fs, "backward": bs},
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+        },
+        "kernels": kernels,
+        "fwd_bwd_tflops": round(fwdbwd_flops, 3),
+        "fwd_bwd_frac_fp64_peak": round(fwdbwd_flops / PEAK_FP64_TFLOPS, 4),
+        "fwd_pairs_per_s": fwd_pairs_s,
+        "direct_launch_ms_per_step": round(sum_ms, 3),
+        "batched_vs_per_subgrid": per_sub,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def per_subgrid_comparison(n, ot, synthetic, np, torch, dev):
+    """Forward on n^3 sub-grids (15% missing 1..9 neighbours): one batched
+    launch vs one single-block launch per target on pre-gathered 24^3 halos
+    (gather not timed), on 1, 8 and 32 streams used round-robin."""
+    batch, M, X = synthetic.config3(n)
+    plan = ot.Plan.from_batch(batch)
+    pairs = plan.pairs()
+    T = batch["T"]
+    Md = torch.from_numpy(M).to(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    L = torch.empty((20, T * 512), dtype=torch.float64, device=dev)
+    f, _ = plan.autotune(Md, Xd, L)
+    times = []
+    for _ in range(3):
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record()
+        plan.multipole_batched(Md, Xd, L, sched=f)
+        s1.record()
+        torch.cuda.synchronize()
+        times.append(s0.elapsed_time(s1))
+    batched_ms = sorted(times)[1]
+    log("per-sub-grid comparison: batched forward %.2f ms" % batched_ms)
+
+    # gather every target's halo: missing neighbours -> zero moments, centres
+    # kept finite; periodic images shifted
+    loc = np.arange(512)
+    lx, ly, lz = loc % 8, (loc // 8) % 8, loc // 64
+    hidx = np.empty((27, 512), np.int64)
+    for slot in range(27):
+        sx, sy, sz = slot % 3, (slot // 3) % 3, slot // 9
+        hidx[slot] = (8 * sx + lx) + 24 * (8 * sy + ly) + 576 * (8 * sz + lz)
+    nbr = batch["nbr"]
+    src = np.where(nbr >= 0, nbr, nbr[:, 13:14])
+    gidx = (src[:, :, None] * 512 + loc[None, None, :]).reshape(T, 27 * 512)
+    order = np.argsort(hidx.reshape(-1))
+    gidx = torch.from_numpy(gidx[:, order]).to(dev)             # (T, 13824) store index
+    miss = torch.from_numpy((nbr < 0)[:, :, None].repeat(512, 2).reshape(T, -1)[:, order]).to(dev)
+    shift = torch.from_numpy(
+        (batch["shift"].astype(np.float64) * batch["period"][None, None, :]).repeat(512, 1)
+        .reshape(T, 27, 512, 3).reshape(T, 27 * 512, 3)[:, order]).to(dev)   # (T, 13824, 3)
+    Mh = torch.empty((T, 20, 13824), dtype=torch.float64, device=dev)
+    Xh = torch.empty((T, 3, 13824), dtype=torch.float64, device=dev)
+    for t0 in range(0, T, 256):
+        t1 = min(T, t0 + 256)
+        g = gidx[t0:t1]
+        mm = Md[:, g].permute(1, 0, 2)
+        mm = torch.where(miss[t0:t1, None, :], torch.zeros_like(mm), mm)
+        Mh[t0:t1] = mm
+        xx = Xd[:, g].permute(1, 0, 2) + shift[t0:t1].permute(0, 2, 1)
+        xx = torch.where(miss[t0:t1, None, :], xx + 1.0e6, xx)
+        Xh[t0:t1] = xx
+    Lh = torch.empty((T, 20, 512), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    res = {"workload": "batched multipole forward, %d^3 sub-grids, 15%% missing 1-9 neighbours"
+                       % n, "targets": T, "pairs": pairs,
+           "batched_ms": round(batched_ms, 3),
+           "batched_pairs_per_s": pairs / (batched_ms * 1e-3)}
+    for nstreams in (1, 8, 32):
+        streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(T):
+            ot.ot_fmm_multipole(Mh[t], Xh[t], Lh[t], stream=streams[t % nstreams])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res["per_subgrid_%dstream_ms" % nstreams] = round(ms, 2)
+        res["speedup_vs_%dstream" % nstreams] = round(ms / batched_ms, 2)
+        log("per-sub-grid launches on %2d stream(s): %.1f ms (%.1fx slower)"
+            % (nstreams, ms, ms / batched_ms))
+    # same numbers as the batched launch (the missing cells add exact zeros)
+    Lb = L.reshape(20, T, 512).permute(1, 0, 2)
+    scale = Lb.abs().amax(dim=2, keepdim=True)
+    res["max_rel_diff_vs_batched"] = float(((Lh - Lb).abs() / scale).max())
+    del Mh, Xh, Lh
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(batch, M, X, w, seconds, np):
+    """The CPU oracle (plain C, OpenMP over all host cores) on a bounded
+    sample of the benchmark workload: forward of k target sub-grids plus the
+    adjoint of the same k store sub-grids, k doubled until the budget is
+    reached. Value: sampled forward pairs / (forward + adjoint time)."""
+    import oracle
+    from oracle import max_threads
+    rng = np.random.default_rng(123)
+    order = rng.permutation(batch["T"])
+    nbr = batch["nbr"]
+    slot_pairs = _slot_pairs(np)
+    k, spent, pairs, used = 1, 0.0, 0, 0
+    while True:
+        sel = order[used:used + k].astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.batched_forward(batch, M, X, tsel=sel)
+        oracle.batched_backward(batch, M, X, w, ssel=sel)
+        spent += time.perf_counter() - t0
+        pairs += int(sum(slot_pairs[s] for t in sel for s in range(27) if nbr[t, s] >= 0))
+        used += k
+        if spent >= seconds or used + 2 * k > batch["T"]:
+            break
+        k = 2 * k if spent < seconds / 4 else k
+    log("cpu oracle: %d sub-grids, %.1f s, %d threads" % (used, spent, max_threads()))
+    return {"value": pairs / spent, "unit": "cell-pair interactions/s", "cores": max_threads(),
+            "kind": "oracle",
+            "sample": "fwd of %d sampled target sub-grids + adjoint of the same %d store "
+                      "sub-grids of the benchmark workload (%d pairs, %.1f s)"
+                      % (used, used, pairs, spent)}
+
+
+def _slot_pairs(np):
+    c = np.arange(512)
+    loc = np.stack([c % 8, (c // 8) % 8, c // 64], axis=1)
+    ti = loc + 8
+    out = []
+    for slot in range(27):
+        off = 8 * np.array([slot % 3, (slot // 3) % 3, slot // 9])
+        tj = loc + off
+        dd = tj[None, :, :] - ti[:, None, :]
+        p = tj[None, :, :] // 2 - ti[:, None, :] // 2
+        out.append(int(np.count_nonzero(((dd * dd).sum(-1) > 16) & ((p * p).sum(-1) <= 16))))
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -24,7 +24,7 @@
  *   - Component order of all 20-vectors: graded lexicographic, x most
  *     significant: 1; x,y,z; xx,xy,xz,yy,yz,zz; xxx,xxy,xxz,xyy,xyz,xzz,yyy,
  *     yyz,yzz,zzz. Arrays are structure-of-arrays: component-major.
- *   - All double pointers are DEVICE pointers (FP64, 8-byte aligned), owned by
+ *   - All double pointers are DEVICE pointers (FP64, 16-byte aligned), owned by
  *     the caller. The library keeps no reference to them after a call returns,
  *     except inside a captured step graph (ot_fmm_step_graph_create).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). The
@@ -140,6 +140,15 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
                              int bwd_sched);
 /* Replays the captured graph on `stream`. EINVAL if none was captured. */
 int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream);
+
+/* Per-kernel timing of a plan's launches (tracing support): while enabled,
+ * every forward / adjoint launch of the plan (not graph replays) is
+ * bracketed by HIP events on its stream. ot_fmm_plan_kernel_times waits for
+ * the recorded events, returns for each kernel -- [0] batched forward,
+ * [1] adjoint source-role pass, [2] adjoint target-role pass -- the summed
+ * duration in ms and the number of launches, and resets the counters. */
+int ot_fmm_plan_timing(ot_fmm_plan plan, int enable);
+int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launches[3]);
 
 /* ---------------------------------------------------------------------------
  * Helpers

@@ -1,7 +1,7 @@
 """MI355X (gfx950) FP64 fast-multipole cell-to-cell interaction kernels.
 
 Thin Python binding of the C ABI in ``include/ot_fmm.h`` (library
-``libotfmm.so`` next to this file, built by ``paper_2303_08058_amd.build``).
+``libotfmm.so`` next to this file, built by ``paper_2303_08058_amd/build.py``).
 Functions keep the C names and only marshal arguments: device pointers of
 float64 torch tensors and the current HIP stream. Every step of the
 computation runs in the HIP kernels; there is no CPU fallback, and importing
@@ -34,7 +34,7 @@ SCHED_W16 = 2
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        "libotfmm.so is not built; run `python -m paper_2303_08058_amd.build` "
+        "libotfmm.so is not built; run `python paper_2303_08058_amd/build.py` "
         "(the HIP library is required, there is no fallback)")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -67,6 +67,12 @@ _lib.ot_fmm_step_graph_create.argtypes = [_P, _P, _P, _P, _P, _P, _P, _I, _I]
 _lib.ot_fmm_step_graph_create.restype = _I
 _lib.ot_fmm_step_graph_launch.argtypes = [_P, _P]
 _lib.ot_fmm_step_graph_launch.restype = _I
+_lib.ot_fmm_plan_timing.argtypes = [_P, _I]
+_lib.ot_fmm_plan_timing.restype = _I
+_lib.ot_fmm_plan_kernel_times.argtypes = [_P, _P, _P]
+_lib.ot_fmm_plan_kernel_times.restype = _I
+
+KERNELS = ("forward", "adjoint_source", "adjoint_target")
 
 
 class OtFmmError(RuntimeError):
@@ -217,6 +223,17 @@ class Plan:
             self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
             _dptr(gL, sl, "gL"), _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"),
             int(fwd_sched), int(bwd_sched)), "ot_fmm_step_graph_create")
+
+    def set_timing(self, enable=True):
+        _check(_lib.ot_fmm_plan_timing(self.handle, 1 if enable else 0), "ot_fmm_plan_timing")
+
+    def kernel_times(self):
+        """{kernel: (total ms, launches)} since the last call (waits for the events)."""
+        ms = np.zeros(3, np.float64)
+        n = np.zeros(3, np.int64)
+        _check(_lib.ot_fmm_plan_kernel_times(self.handle, ms.ctypes.data_as(_P),
+                                             n.ctypes.data_as(_P)), "ot_fmm_plan_kernel_times")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def step_graph_launch(self, stream=None):
         _check(_lib.ot_fmm_step_graph_launch(self.handle, _stream(stream)),

@@ -1,6 +1,7 @@
 """Build the HIP library libotfmm.so in-tree (hipcc, gfx950).
 
-Usage: python -m paper_2303_08058_amd.build
+Usage: python paper_2303_08058_amd/build.py   (run as a script: importing the
+package requires the library this builds)
 """
 from __future__ import annotations
 

@@ -487,59 +487,111 @@ struct ModeTraits {
     static constexpr int nacc = adjoint ? 54 : 20;
 };
 
+// LDS plane layout: cell-major, Layout::stride doubles per cell -- the
+// centre (x, y, z), then the nq scaled source components, then padding. A
+// pair is read with 16-byte loads from one base address (immediate offsets).
+// The cell stride in 16-byte units is odd, so the 8 lanes served per LDS
+// cycle by a 16-byte read -- 8 different cells modulo 8 in the mirrored lane
+// pattern -- fall on disjoint banks.
+template <int MODE>
+struct Layout {
+    static constexpr int nc = ModeTraits<MODE>::nc;
+    static constexpr int nvec = (nc + 1) / 2;                               // 16-byte reads per cell
+    static constexpr int stride = (nvec % 2 == 1) ? 2 * nvec : 2 * nvec + 2;  // doubles per cell
+};
+
 template <int MODE, int NW>
 constexpr int lds_doubles()
 {
-    constexpr int plane = ModeTraits<MODE>::nc * kPlane;
+    constexpr int plane = Layout<MODE>::stride * kPlane;
     constexpr int merge = (NW == 16) ? 20 * kSub3 : 0;
     return plane > merge ? plane : merge;
 }
 
-// Stage halo z-plane zs of the owner's neighbourhood into LDS as
-// lds[c][y * 24 + x]: components 0..nq-1 scaled sources, nq..nq+2 centres.
-template <int MODE, int NW>
-__device__ __forceinline__ void stage_plane(const KParams& p, int owner, int zs, double* lds)
+// Staging of one halo z-plane: every global load of the calling thread is
+// issued first, then the values are scaled and written into the LDS plane.
+// Work unit ("chunk"): one component of one 8x8-cell block of the plane (one
+// of the 3x3 neighbour sub-grids crossing it); lane l takes cell
+// (l % 8, l / 8) of the block, so a wavefront reads 512 contiguous bytes.
+// Chunks are dealt to wavefronts round-robin, which keeps the component, the
+// block and all their address math wave-uniform (scalar registers); the
+// loop over chunks is branch-free (uniform selects) so that all loads of a
+// wavefront are in flight together. A missing neighbour is read at block 0
+// (valid memory) and replaced by zero moments and a far centre.
+template <int MODE>
+struct Chunk {
+    const double* src;  // component base, already offset to the cell
+    double scale, add, fill;
+    bool present;
+};
+
+template <int MODE>
+__device__ __forceinline__ Chunk<MODE> chunk_of(const KParams& p, const int4* rel, int zs, int u,
+                                                int lane)
 {
     using T = ModeTraits<MODE>;
-    constexpr int NT = NW * 64;
-    const int tid = threadIdx.x;
+    const int c = u / 9;  // 0..2 centre, 3.. sources
+    const int bxy = u - 9 * c;
+    const int by = bxy / 3, bx = bxy - 3 * by;
+    const bool isx = c < 3;
+    const int cm = isx ? 0 : c - 3;
+    const int cx = isx ? c : 0;
+    Chunk<MODE> ch;
     if constexpr (T::halo) {
-        for (int e = tid; e < T::nc * kPlane; e += NT) {
-            const int c = e / kPlane;
-            const int i = e - c * kPlane;
-            double v;
-            if (c < T::nq)
-                v = p.mom[(long)c * kHalo3 + zs * kPlane + i] * c_scale_fwd[c];
-            else
-                v = p.pos[(long)(c - T::nq) * kHalo3 + zs * kPlane + i];
-            lds[e] = v;
-        }
+        const long h = (long)zs * kPlane + (by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7);
+        ch.src = (isx ? p.pos + (long)cx * kHalo3 : p.mom + (long)cm * kHalo3) + h;
+        ch.scale = isx ? 1.0 : c_scale_fwd[cm];
+        ch.add = 0.0;
+        ch.fill = 0.0;
+        ch.present = true;
     } else {
-        const int bz = zs >> 3, lz = zs & 7;
-        const int4* rel = p.rel + (long)owner * 27 + 9 * bz;
-        for (int e = tid; e < T::nc * kPlane; e += NT) {
-            const int c = e / kPlane;
-            const int rem = e - c * kPlane;
-            const int bxy = rem >> 6, l = rem & 63;
-            const int by = bxy / 3, bx = bxy - 3 * by;
-            const int4 r = rel[bxy];
-            const long lidx = l + 64 * lz;
-            double v;
-            if (c < T::nq) {
-                const double s = (MODE == MODE_B2_STORE) ? c_scale_rev[c] : c_scale_fwd[c];
-                v = r.x >= 0 ? p.mom[(long)c * p.mom_stride + (long)r.x * kSub3 + lidx] * s : 0.0;
-            } else {
-                const int k = c - T::nq;
-                if (r.x >= 0) {
-                    const int sh = (int)(int8_t)((r.z >> (8 * k)) & 0xff);
-                    v = p.pos[(long)k * p.pos_stride + (long)r.y * kSub3 + lidx] +
-                        (double)sh * p.period[k];
-                } else {
-                    v = kFar;
-                }
-            }
-            lds[c * kPlane + (by * 8 + (l >> 3)) * kHalo + bx * 8 + (l & 7)] = v;
-        }
+        const int4 rr = rel[9 * (zs >> 3) + bxy];  // uniform address: scalar load
+        ch.present = rr.x >= 0;
+        const long blk = ch.present ? (isx ? rr.y : rr.x) : 0;
+        const long lidx = blk * kSub3 + 64 * (zs & 7) + lane;
+        ch.src = (isx ? p.pos + (long)cx * p.pos_stride : p.mom + (long)cm * p.mom_stride) + lidx;
+        const double sc = (MODE == MODE_B2_STORE) ? c_scale_rev[cm] : c_scale_fwd[cm];
+        ch.scale = isx ? 1.0 : sc;
+        ch.add = isx ? (double)(int)(int8_t)((rr.z >> (8 * cx)) & 0xff) * p.period[cx] : 0.0;
+        ch.fill = isx ? kFar : 0.0;
+    }
+    return ch;
+}
+
+template <int MODE>
+__device__ __forceinline__ int chunk_lds_index(int u, int lane)
+{
+    const int c = u / 9;
+    const int bxy = u - 9 * c;
+    const int by = bxy / 3, bx = bxy - 3 * by;
+    return ((by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7)) * Layout<MODE>::stride + c;
+}
+
+template <int MODE, int NW>
+__device__ __forceinline__ void stage_plane(const KParams& p, const int4* rel, int zs, int wave,
+                                            int lane, double* lds)
+{
+    using T = ModeTraits<MODE>;
+    constexpr int NCH = 9 * T::nc;   // chunks per plane
+    constexpr int FULL = NCH / NW;   // chunks every wavefront has
+    const bool tail = wave + FULL * NW < NCH;
+    double raw[FULL + 1];
+#pragma unroll
+    for (int k = 0; k < FULL; ++k) raw[k] = *chunk_of<MODE>(p, rel, zs, wave + k * NW, lane).src;
+    raw[FULL] = 0.0;
+    if (tail) raw[FULL] = *chunk_of<MODE>(p, rel, zs, wave + FULL * NW, lane).src;
+#pragma unroll
+    for (int k = 0; k < FULL; ++k) {
+        const int u = wave + k * NW;
+        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
+        lds[chunk_lds_index<MODE>(u, lane)] =
+            ch.present ? __builtin_fma(raw[k], ch.scale, ch.add) : ch.fill;
+    }
+    if (tail) {
+        const int u = wave + FULL * NW;
+        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
+        lds[chunk_lds_index<MODE>(u, lane)] =
+            ch.present ? __builtin_fma(raw[FULL], ch.scale, ch.add) : ch.fill;
     }
 }
 
@@ -547,6 +599,7 @@ template <int MODE, int NW>
 __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
 {
     using T = ModeTraits<MODE>;
+    using Lay = Layout<MODE>;
     static_assert(NW == 8 || NW == 16, "8 or 16 wavefronts");
     static_assert(!(T::adjoint && NW != 8), "adjoint passes use 8 wavefronts");
     __shared__ double lds[lds_doubles<MODE, NW>()];
@@ -555,6 +608,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int owner = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
+    const int4* s_rel = T::halo ? nullptr : p.rel + (long)owner * 27;  // this owner's relations
     const int zt = (NW == 16) ? (wave >> 1) : wave;
     const int half = (NW == 16) ? (wave & 1) : 0;
     const int xt = lane & 7, yt = lane >> 3;
@@ -581,50 +635,60 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
 #pragma unroll
     for (int a = 0; a < T::nacc; ++a) acc[a] = 0.0;
 
-    const int lane_base = (8 + yt) * kHalo + 8 + xt;
-    const int step_y = sgy * kHalo;
+    // addresses in 16-byte units of the LDS plane
+    constexpr int cs = Lay::stride / 2;
+    const int lane_off = ((8 + yt) * kHalo + 8 + xt) * cs;
+    const int step_x = sgx * cs;
+    const int step_y = sgy * kHalo * cs;
+    const double2* lds2 = reinterpret_cast<const double2*>(lds);
 
     for (int zs = 0; zs < kHalo; ++zs) {
         __syncthreads();
-        stage_plane<MODE, NW>(p, owner, zs, lds);
+        stage_plane<MODE, NW>(p, s_rel, zs, wave, lane, lds);
         __syncthreads();
         const int dz = zs - (8 + zt);
-        if (dz < -kReach || dz > kReach) continue;
-        const int* rg = c_stencil.range[pz][dz + kReach];
-        int r0 = rg[0], r1 = rg[2];
-        if (NW == 16) {
-            if (half == 0)
-                r1 = rg[1];
-            else
-                r0 = rg[1];
-        }
-        for (int r = r0; r < r1; ++r) {
-            const uint32_t w = c_stencil.rows[pz][r];
-            const int dy = (int)(int8_t)(w & 0xff);
-            const int dx0 = (int)(int8_t)((w >> 8) & 0xff);
-            const int n = (int)(w >> 16);
-            int idx = lane_base + dy * step_y + dx0 * sgx;
-            for (int k = 0; k < n; ++k, idx += sgx) {
-                const double rx = xi - lds[(T::nq + 0) * kPlane + idx];
-                const double ry = yi - lds[(T::nq + 1) * kPlane + idx];
-                const double rz = zi - lds[(T::nq + 2) * kPlane + idx];
-                double q[T::nq];
+        if (dz >= -kReach && dz <= kReach) {
+            const int* rg = c_stencil.range[pz][dz + kReach];
+            int r0 = rg[0], r1 = rg[2];
+            if (NW == 16) {
+                if (half == 0)
+                    r1 = rg[1];
+                else
+                    r0 = rg[1];
+            }
+            for (int r = r0; r < r1; ++r) {
+                const uint32_t w = c_stencil.rows[pz][r];
+                const int dy = (int)(int8_t)(w & 0xff);
+                const int dx0 = (int)(int8_t)((w >> 8) & 0xff);
+                const int n = (int)(w >> 16);
+                int off = lane_off + dy * step_y + dx0 * step_x;
+                for (int k = 0; k < n; ++k, off += step_x) {
+                    double f[2 * Lay::nvec];
 #pragma unroll
-                for (int c = 0; c < T::nq; ++c) q[c] = lds[c * kPlane + idx];
-                if constexpr (MODE == MODE_MONO_HALO) {
-                    double G[20];
-                    green<3>(rx, ry, rz, G);
+                    for (int j = 0; j < Lay::nvec; ++j) {
+                        const double2 v = lds2[off + j];
+                        f[2 * j] = v.x;
+                        f[2 * j + 1] = v.y;
+                    }
+                    const double rx = xi - f[0];
+                    const double ry = yi - f[1];
+                    const double rz = zi - f[2];
+                    const double* q = f + 3;
+                    if constexpr (MODE == MODE_MONO_HALO) {
+                        double G[20];
+                        green<3>(rx, ry, rz, G);
 #pragma unroll
-                    for (int a = 0; a < 20; ++a) acc[a] = __builtin_fma(q[0], G[a], acc[a]);
-                } else if constexpr (!T::adjoint) {
-                    double G[20];
-                    green<3>(rx, ry, rz, G);
-                    contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
-                } else {
-                    double G[35];
-                    green<4>(rx, ry, rz, G);
-                    contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
-                    contract_e(acc + 20, q, G, std::make_integer_sequence<int, 34>{});
+                        for (int a = 0; a < 20; ++a) acc[a] = __builtin_fma(q[0], G[a], acc[a]);
+                    } else if constexpr (!T::adjoint) {
+                        double G[20];
+                        green<3>(rx, ry, rz, G);
+                        contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
+                    } else {
+                        double G[35];
+                        green<4>(rx, ry, rz, G);
+                        contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
+                        contract_e(acc + 20, q, G, std::make_integer_sequence<int, 34>{});
+                    }
                 }
             }
         }
@@ -713,7 +777,7 @@ int ensure_device()
     return OT_FMM_OK;
 }
 
-bool aligned8(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 template <int MODE, int NW>
 int launch(const KParams& kp, int nblocks, hipStream_t stream)
@@ -747,9 +811,50 @@ struct ot_fmm_plan_s {
     int tuned_fwd = 0, tuned_bwd = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // per-kernel timing (forward, adjoint source pass, adjoint target pass)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[3];
+    size_t ev_used[3] = {0, 0, 0};
 };
 
 namespace {
+
+// Event pair bracketing one launch of kernel `which` on `stream`, or a null
+// pair when timing is off. Events come from a per-plan pool.
+int timing_begin(ot_fmm_plan plan, int which, hipStream_t stream,
+                 std::pair<hipEvent_t, hipEvent_t>* ev)
+{
+    *ev = {nullptr, nullptr};
+    if (!plan->timing) return OT_FMM_OK;
+    auto& pool = plan->ev_pool[which];
+    size_t& used = plan->ev_used[which];
+    if (used == pool.size()) {
+        hipEvent_t a, b;
+        OT_HIP(hipEventCreate(&a));
+        OT_HIP(hipEventCreate(&b));
+        pool.emplace_back(a, b);
+    }
+    *ev = pool[used++];
+    OT_HIP(hipEventRecord(ev->first, stream));
+    return OT_FMM_OK;
+}
+
+int timing_end(const std::pair<hipEvent_t, hipEvent_t>& ev, hipStream_t stream)
+{
+    if (ev.second) OT_HIP(hipEventRecord(ev.second, stream));
+    return OT_FMM_OK;
+}
+
+template <int MODE, int NW>
+int launch_timed(ot_fmm_plan plan, int which, const KParams& kp, int nblocks, hipStream_t stream)
+{
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    int rc = timing_begin(plan, which, stream, &ev);
+    if (rc) return rc;
+    rc = launch<MODE, NW>(kp, nblocks, stream);
+    if (rc) return rc;
+    return timing_end(ev, stream);
+}
 
 int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, int sched,
                 hipStream_t stream)
@@ -767,8 +872,8 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
     kp.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
     sched = pick_fwd(sched, plan->tuned_fwd);
-    if (sched == OT_FMM_SCHED_W8) return launch<MODE_FWD_STORE, 8>(kp, plan->T, stream);
-    if (sched == OT_FMM_SCHED_W16) return launch<MODE_FWD_STORE, 16>(kp, plan->T, stream);
+    if (sched == OT_FMM_SCHED_W8) return launch_timed<MODE_FWD_STORE, 8>(plan, 0, kp, plan->T, stream);
+    if (sched == OT_FMM_SCHED_W16) return launch_timed<MODE_FWD_STORE, 16>(plan, 0, kp, plan->T, stream);
     return fail(OT_FMM_EINVAL, "unknown forward schedule");
 }
 
@@ -794,7 +899,7 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b2.out_stride = NS;
     b2.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) b2.period[k] = plan->period[k];
-    int rc = launch<MODE_B2_STORE, 8>(b2, plan->S, stream);
+    int rc = launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, stream);
     if (rc) return rc;
     // target role: owners are targets, sources their neighbours' cells
     KParams b1{};
@@ -811,7 +916,7 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b1.out_stride = NS;
     b1.out_blk = plan->d_tgt;
     for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
-    return launch<MODE_B1_STORE, 8>(b1, plan->T, stream);
+    return launch_timed<MODE_B1_STORE, 8>(plan, 2, b1, plan->T, stream);
 }
 
 int check_plan(ot_fmm_plan plan)
@@ -826,6 +931,11 @@ int check_plan(ot_fmm_plan plan)
 
 void free_plan_memory(ot_fmm_plan p)
 {
+    for (auto& pool : p->ev_pool)
+        for (auto& ev : pool) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->graph_exec = nullptr;
@@ -888,8 +998,8 @@ const char* ot_fmm_last_error(void) { return g_last_error.c_str(); }
 int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stream)
 {
     g_last_error.clear();
-    if (!aligned8(mass) || !aligned8(com) || !aligned8(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (!aligned16(mass) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     int rc = ensure_device();
     if (rc) return rc;
     KParams kp{};
@@ -902,8 +1012,8 @@ int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stre
 int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream)
 {
     g_last_error.clear();
-    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     int rc = ensure_device();
     if (rc) return rc;
     KParams kp{};
@@ -1021,8 +1131,8 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     if (sched < 0 || sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
     return fwd_batched(plan, M, com, L, sched, (hipStream_t)stream);
 }
@@ -1034,8 +1144,8 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned8(M) || !aligned8(com) || !aligned8(gL) || !aligned8(gM) || !aligned8(gcom))
-        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(gM) || !aligned16(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     if (gM == M || gM == gL || gcom == com || (const double*)gcom == gL || (const double*)gM == com)
         return fail(OT_FMM_EINVAL, "outputs alias inputs");
     if (sched != OT_FMM_SCHED_AUTO && sched != OT_FMM_SCHED_W8)
@@ -1050,10 +1160,10 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     const bool with_bwd = gL || gM || gcom;
-    if (with_bwd && (!aligned8(gL) || !aligned8(gM) || !aligned8(gcom)))
+    if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0, e1;
@@ -1103,10 +1213,10 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned pointer");
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     const bool with_bwd = gL || gM || gcom;
-    if (with_bwd && (!aligned8(gL) || !aligned8(gM) || !aligned8(gcom)))
+    if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
     if (fwd_sched < 0 || fwd_sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
     if (with_bwd && bwd_sched != OT_FMM_SCHED_AUTO && bwd_sched != OT_FMM_SCHED_W8)
@@ -1119,8 +1229,11 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
+    const bool timing = plan->timing;
+    plan->timing = false;  // no timing events inside the graph
     rc = fwd_batched(plan, M, com, L, fwd_sched, cs);
     if (!rc && with_bwd) rc = bwd_batched(plan, M, com, gL, gM, gcom, bwd_sched, cs);
+    plan->timing = timing;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
     if (rc) {
@@ -1148,6 +1261,37 @@ int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream)
     if (rc) return rc;
     if (!plan->graph_exec) return fail(OT_FMM_EINVAL, "no step graph captured");
     OT_HIP(hipGraphLaunch(plan->graph_exec, (hipStream_t)stream));
+    return OT_FMM_OK;
+}
+
+int ot_fmm_plan_timing(ot_fmm_plan plan, int enable)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    plan->timing = enable != 0;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launches[3])
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!ms_total || !launches) return fail(OT_FMM_EINVAL, "null output");
+    for (int w = 0; w < 3; ++w) {
+        double tot = 0.0;
+        for (size_t i = 0; i < plan->ev_used[w]; ++i) {
+            const auto& ev = plan->ev_pool[w][i];
+            OT_HIP(hipEventSynchronize(ev.second));
+            float ms = 0.0f;
+            OT_HIP(hipEventElapsedTime(&ms, ev.first, ev.second));
+            tot += ms;
+        }
+        ms_total[w] = tot;
+        launches[w] = (int64_t)plan->ev_used[w];
+        plan->ev_used[w] = 0;
+    }
     return OT_FMM_OK;
 }
 

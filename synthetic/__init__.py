@@ -24,6 +24,8 @@ Layouts (shared conventions of the C ABI):
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 NM = 20
@@ -136,25 +138,44 @@ def multipole_block(seed=1002, sigma=3.0, q=0.7, sep=10.0):
 # --------------------------------------------------------------------------
 # batched stores
 # --------------------------------------------------------------------------
-def store_field(n, rng, sigma1, sigma2, q, sep=10.0, chunk=1024):
+def store_field(n, rng, sigma1, sigma2, q, sep=10.0, chunk=512, workers=None):
     """Store of n^3 sub-grids (store id s = sx + n sy + n^2 sz) covering an
-    (8n)^3-cell domain with two blobs at the domain centre -+ (sep/2, 0, 0)."""
+    (8n)^3-cell domain with two blobs at the domain centre -+ (sep/2, 0, 0).
+
+    Chunks of `chunk` sub-grids draw their child jitter from their own
+    generator, seeded from one draw of `rng` and the chunk index, so the
+    result does not depend on the number of worker threads."""
     S = n ** 3
     M = np.empty((NM, S * SUB3), np.float64)
     X = np.empty((3, S * SUB3), np.float64)
     centres, sigmas, amps = blob_params([4.0 * n] * 3, sigma1, sigma2, q, sep)
     lz, ly, lx = np.meshgrid(np.arange(SUB), np.arange(SUB), np.arange(SUB), indexing="ij")
     loc = np.stack([lx.ravel(), ly.ravel(), lz.ravel()], axis=1)
-    for s0 in range(0, S, chunk):
+    base = int(rng.integers(0, 2 ** 62))
+
+    def work(ci):
+        s0 = ci * chunk
         s1 = min(S, s0 + chunk)
         sid = np.arange(s0, s1)
         sc = np.stack([sid % n, (sid // n) % n, sid // (n * n)], axis=1)
         g = (SUB * sc[:, None, :] + loc[None, :, :]).reshape(-1, 3)
-        xc = children_of_cells(g, rng)
+        crng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([base, ci])))
+        xc = children_of_cells(g, crng)
         mc = density(xc, centres, sigmas, amps) * 0.125
         Mc, Xc = cells_from_children(xc, mc)
         M[:, s0 * SUB3:s1 * SUB3] = Mc
         X[:, s0 * SUB3:s1 * SUB3] = Xc
+
+    nchunks = (S + chunk - 1) // chunk
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or nchunks == 1:
+        for ci in range(nchunks):
+            work(ci)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(work, range(nchunks)))
     return M, X
 
 

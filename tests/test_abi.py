@@ -22,8 +22,9 @@ def declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(LIB):
-        from paper_2303_08058_amd.build import build
-        build()
+        import subprocess
+        import sys
+        subprocess.check_call([sys.executable, os.path.join(ROOT, "paper_2303_08058_amd", "build.py")])
     return ctypes.CDLL(LIB)
 
 

@@ -148,3 +148,218 @@ def test_backward_small_periodic_missing(ot):
     plan.multipole_backward(_dev(M), _dev(X), _dev(w), gM, gX)
     assert_parity(_host(gM), gM_ref, TOL, what="gM periodic")
     assert_parity(_host(gX), gX_ref, TOL, what="gX periodic")
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_zero_masses_give_exact_zero(ot):
+    b = synthetic.multipole_block(1002)
+    L = _empty(20, 512)
+    ot.ot_fmm_multipole(_dev(np.zeros((20, 13824))), _dev(b["com"]), L)
+    assert np.all(_host(L) == 0.0)
+
+
+def test_isolated_target_and_single_target(ot):
+    """One target whose 26 neighbours are all missing (only its own pairs),
+    next to a target with a full neighbourhood, in one launch."""
+    batch, M, X = synthetic.batched_config(3, 51, periodic=True)
+    tg = np.array([0, 13], np.int32)
+    nbr = batch["nbr"][tg].copy()
+    nbr[0, [s for s in range(27) if s != 13]] = -1
+    b = {"S": 27, "T": 2, "tgt": tg, "nbr": nbr, "shift": batch["shift"][tg],
+         "period": batch["period"]}
+    ref = oracle.batched_forward(b, M, X)
+    plan = ot.Plan.from_batch(b)
+    assert plan.pairs() == 173536 + 921088
+    L = _empty(20, 2 * 512)
+    plan.multipole_batched(_dev(M), _dev(X), L)
+    assert_parity(_host(L), ref, TOL, what="isolated")
+
+
+def test_autograd_function_matches_oracle(ot):
+    import torch
+    batch, M, X = synthetic.batched_config(2, 61, missing_frac=0.5)
+    plan = ot.Plan.from_batch(batch)
+    Md = _dev(M).requires_grad_(True)
+    Xd = _dev(X).requires_grad_(True)
+    w = synthetic.weights(batch["T"], 62)
+    L = ot.multipole(Md, Xd, plan)
+    (L * _dev(w)).sum().backward()
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w)
+    assert_parity(_host(Md.grad), gM_ref, TOL, what="autograd gM")
+    assert_parity(_host(Xd.grad), gX_ref, TOL, what="autograd gX")
+    assert L.dtype == torch.float64
+
+
+def test_step_graph_replays_match_eager(ot):
+    """The captured forward+adjoint graph, replayed several times with eager
+    work and synchronisations in between, reproduces the eager results
+    bitwise on every replay."""
+    import torch
+    batch, M, X = synthetic.batched_config(3, 71, missing_frac=0.3)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd = _dev(M), _dev(X)
+    wd = _dev(synthetic.weights(batch["T"], 72))
+    NS, NT = batch["S"] * 512, batch["T"] * 512
+    L0, gM0, gX0 = _empty(20, NT), _empty(20, NS), _empty(3, NS)
+    plan.multipole_batched(Md, Xd, L0)
+    plan.multipole_backward(Md, Xd, wd, gM0, gX0)
+    L, gM, gX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
+    plan.step_graph_create(Md, Xd, L, wd, gM, gX)
+    for rep in range(3):
+        L.fill_(float("nan"))
+        gX.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.step_graph_launch()
+        torch.cuda.synchronize()
+        assert torch.equal(L, L0) and torch.equal(gM, gM0) and torch.equal(gX, gX0), rep
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        del junk
+
+
+def test_autotune_choices_are_valid_and_exact(ot):
+    batch, M, X = synthetic.batched_config(3, 81, missing_frac=0.3)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd = _dev(M), _dev(X)
+    L = _empty(20, batch["T"] * 512)
+    f, b = plan.autotune(Md, Xd, L)
+    assert f in (1, 2) and b == 1
+    plan.multipole_batched(Md, Xd, L)   # AUTO -> tuned
+    ref = oracle.batched_forward(batch, M, X, tsel=[0, 5, 26])
+    got = _host(L).reshape(20, 27, 512)[:, [0, 5, 26]].reshape(20, -1)
+    assert_parity(got, ref, TOL, what="autotuned")
+
+
+def test_invalid_schedule_rejected(ot):
+    batch, M, X = synthetic.batched_config(2, 91)
+    plan = ot.Plan.from_batch(batch)
+    L = _empty(20, batch["T"] * 512)
+    with pytest.raises(ot.OtFmmError):
+        plan.multipole_batched(_dev(M), _dev(X), L, sched=7)
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, sampled outputs
+# ---------------------------------------------------------------------------
+def _sample_targets(batch, n_missing, n_random, seed):
+    rng = np.random.default_rng(seed)
+    miss = batch.get("missing_targets", np.zeros(0, np.int32))
+    pick = list(rng.choice(miss, size=min(n_missing, len(miss)), replace=False)) if len(miss) else []
+    rest = np.setdiff1d(np.arange(batch["T"]), pick)
+    pick += list(rng.choice(rest, size=n_random, replace=False))
+    return np.array(sorted(set(int(v) for v in pick)), np.int32)
+
+
+def _cols(a, sel):
+    return a.reshape(a.shape[0], -1, 512)[:, sel].reshape(a.shape[0], -1)
+
+
+@pytest.mark.parametrize("sched", [1, 2])
+def test_config3_forward_sampled(ot, sched):
+    """16^3 sub-grids, periodic, 15% missing 1-9 neighbours: every output of
+    the launch is produced, a seeded sample of targets (half of them with
+    missing neighbours) is compared with the oracle."""
+    batch, M, X = synthetic.config3()
+    plan = ot.Plan.from_batch(batch)
+    L = _empty(20, batch["T"] * 512)
+    plan.multipole_batched(_dev(M), _dev(X), L, sched=sched)
+    got = _host(L)
+    assert np.all(np.isfinite(got))
+    sel = _sample_targets(batch, 12, 12, 3)
+    ref, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True)
+    assert_parity(_cols(got, sel), ref, TOL, what="config3", A=A)
+
+
+def test_config4_adjoint_sampled_and_fd():
+    """8^3 sub-grids on an open domain, w ~ N(0,1): sampled store sub-grids
+    (corner, edge, face, interior, random) against the oracle's gradient,
+    and 256 seeded entries against central differences of the GPU forward,
+    outputs differenced first. Centres of mass: step 1e-6 (the rounding noise
+    of the differenced loss, ~1e-13, limits this check to ~1e-6 relative).
+    Moments: L is linear in them, so a unit step is exact up to rounding."""
+    import torch
+    import paper_2303_08058_amd as ot
+    batch, M, X = synthetic.config4()
+    w = synthetic.weights(batch["T"], 1004 + 100)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    NS = batch["S"] * 512
+    gM, gX = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward(Md, Xd, wd, gM, gX)
+    gM_h, gX_h = _host(gM), _host(gX)
+    assert np.all(np.isfinite(gM_h)) and np.all(np.isfinite(gX_h))
+    n = 8
+    corner, edge, face, inner = 0, 3, 3 + n * 3, 3 + n * 3 + n * n * 3
+    rng = np.random.default_rng(4)
+    sel = np.array(sorted({corner, edge, face, inner, *rng.choice(batch["S"], 6, replace=False)}),
+                   np.int32)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=sel)
+    print("config4 gM worst", assert_parity(_cols(gM_h, sel), gM_ref, TOL, what="config4 gM"))
+    print("config4 gX worst", assert_parity(_cols(gX_h, sel), gX_ref, TOL, what="config4 gX"))
+
+    # central differences of the GPU forward
+    L = torch.empty((20, batch["T"] * 512), dtype=torch.float64, device="cuda")
+    Lp, Lm = torch.empty_like(L), torch.empty_like(L)
+    ent = rng.integers(0, NS, 256)
+    comp = rng.integers(0, 23, 256)
+    h = 1e-6
+    fd, an = [], []
+    for e, c in zip(ent, comp):
+        if c < 20:
+            step = 1.0
+            arr, idx, grad = Md, (int(c), int(e)), gM_h[c, e]
+        else:
+            step = h
+            arr, idx, grad = Xd, (int(c) - 20, int(e)), gX_h[c - 20, e]
+        orig = arr[idx].item()
+        arr[idx] = orig + step
+        plan.multipole_batched(Md, Xd, Lp)
+        arr[idx] = orig - step
+        plan.multipole_batched(Md, Xd, Lm)
+        arr[idx] = orig
+        d = float(((Lp - Lm) * wd).sum()) / (2 * step)
+        fd.append(d)
+        an.append(grad)
+    fd, an = np.array(fd), np.array(an)
+    is_m = comp < 20
+    # L is linear in M: differences are exact up to rounding
+    assert np.max(np.abs(fd[is_m] - an[is_m])) <= 1e-9 * np.max(np.abs(an[is_m]))
+    assert np.max(np.abs(fd[~is_m] - an[~is_m])) <= 1e-5 * np.max(np.abs(an[~is_m]))
+    print("fd max deviation: moments %.2e, centres %.2e (relative to max |grad|)" % (
+        np.max(np.abs(fd[is_m] - an[is_m])) / np.max(np.abs(an[is_m])),
+        np.max(np.abs(fd[~is_m] - an[~is_m])) / np.max(np.abs(an[~is_m]))))
+
+
+def test_config5_step_graph_sampled():
+    """32^3 sub-grids (16.8M cells), periodic, 20% missing: the benchmark's
+    launch configuration (autotuned schedules, captured forward+adjoint graph)
+    with sampled targets and store sub-grids checked against the oracle."""
+    import torch
+    import paper_2303_08058_amd as ot
+    batch, M, X = synthetic.config5()
+    w = synthetic.weights(batch["T"], 2005)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    NS, NT = batch["S"] * 512, batch["T"] * 512
+    L = torch.empty((20, NT), dtype=torch.float64, device="cuda")
+    gM = torch.empty((20, NS), dtype=torch.float64, device="cuda")
+    gX = torch.empty((3, NS), dtype=torch.float64, device="cuda")
+    fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
+    plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
+    L.fill_(float("nan"))
+    gM.fill_(float("nan"))
+    gX.fill_(float("nan"))
+    plan.step_graph_launch()
+    torch.cuda.synchronize()
+    sel = _sample_targets(batch, 4, 4, 5)
+    Ls = L.reshape(20, -1, 512)[:, torch.from_numpy(sel).long().cuda()].reshape(20, -1).cpu().numpy()
+    ref, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True)
+    assert_parity(Ls, ref, TOL, what="config5 L", A=A)
+    ssel = sel[:4]
+    gMs = gM.reshape(20, -1, 512)[:, torch.from_numpy(ssel).long().cuda()].reshape(20, -1).cpu().numpy()
+    gXs = gX.reshape(3, -1, 512)[:, torch.from_numpy(ssel).long().cuda()].reshape(3, -1).cpu().numpy()
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=ssel)
+    print("config5 gM worst", assert_parity(gMs, gM_ref, TOL, what="config5 gM"))
+    print("config5 gX worst", assert_parity(gXs, gX_ref, TOL, what="config5 gX"))
+    assert bool(torch.isfinite(L).all()) and bool(torch.isfinite(gM).all()) and bool(torch.isfinite(gX).all())
