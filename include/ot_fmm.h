@@ -57,9 +57,11 @@ enum {
 
 /* Schedules (how a target sub-grid's 512 cells are spread over wavefronts).
  * Both keep one work-group per target sub-grid and one staged source z-plane
- * in LDS; lanes are the 8x8 target cells of one z-plane. */
+ * in LDS; lanes are the 8x8 target cells of one z-plane. For the adjoint the
+ * schedule applies to its target-role pass; the source-role pass always uses
+ * 8 wavefronts. */
 enum {
-    OT_FMM_SCHED_AUTO = 0,  /* the plan's tuned choice (ot_fmm_autotune), else the default */
+    OT_FMM_SCHED_AUTO = 0,  /* the plan's tuned choice (ot_fmm_autotune), else W16 */
     OT_FMM_SCHED_W8 = 1,    /* 8 wavefronts: one per target z-plane */
     OT_FMM_SCHED_W16 = 2    /* 16 wavefronts: two per target z-plane, stencil rows split */
 };
@@ -119,7 +121,7 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
  * gM and gcom are OVERWRITTEN; cells of store sub-grids that no target
  * references get 0. Gather form (no atomics): one pass over each store
  * sub-grid's source role, then one over each target's own cells. gM/gcom
- * must not alias M, com or gL. Schedule OT_FMM_SCHED_W8 (or AUTO). */
+ * must not alias M, com or gL. */
 int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* com,
                               const double* gL, double* gM, double* gcom, int sched,
                               void* stream);

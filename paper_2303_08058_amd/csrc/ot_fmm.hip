@@ -373,70 +373,133 @@ __device__ __forceinline__ void green(double x, double y, double z, double* G)
     }
 }
 
-// L[A] += sum_{B: |A|+|B| <= 3} q[B] G[A+B]      (forward contraction, 84 FMAs)
-template <int A, int B>
-__device__ __forceinline__ void term_fwd(double* L, const double* q, const double* G)
+// ---------------------------------------------------------------------------
+// Trace-reduced contractions. Every derivative of 1/r of order >= 2 is
+// trace-free (Laplace's equation): G_{g+xx} + G_{g+yy} + G_{g+zz} = 0. So
+//  * source side: a complete order-2 or order-3 shell of source components
+//    contracts through 16 combinations instead of 20 -- q_xx - q_zz and
+//    q_yy - q_zz (paired with G_{.+xx}, G_{.+yy}); q_xxx - q_xzz,
+//    q_xyy - q_xzz, q_xxy - q_yzz, q_yyy - q_yzz, q_xxz - q_zzz,
+//    q_yyz - q_zzz and q_xyz for order 3;
+//  * output side: within a group of outputs of one order and one truncation,
+//    every output whose z exponent is >= 2 follows from two others,
+//    L_{g+zz} = -(L_{g+xx} + L_{g+yy}), and is rebuilt after the sum.
+// The results equal the plain contraction up to rounding.
+// ---------------------------------------------------------------------------
+constexpr int kNRed = 16;
+// reduced component b = q[kRedP[b]] - q[kRedS[b]] (kRedS = -1: q[kRedP[b]]);
+// it pairs with G_{g + kRedP[b]}
+constexpr int kRedP[kNRed] = {0, 1, 2, 3, 4, 7, 5, 6, 8, 10, 13, 11, 16, 12, 17, 14};
+constexpr int kRedS[kNRed] = {-1, -1, -1, -1, 9, 9, -1, -1, -1, 15, 15, 18, 18, 19, 19, -1};
+__constant__ int c_red_src[kNRed][2] = {
+    {kRedP[0], kRedS[0]},   {kRedP[1], kRedS[1]},   {kRedP[2], kRedS[2]},   {kRedP[3], kRedS[3]},
+    {kRedP[4], kRedS[4]},   {kRedP[5], kRedS[5]},   {kRedP[6], kRedS[6]},   {kRedP[7], kRedS[7]},
+    {kRedP[8], kRedS[8]},   {kRedP[9], kRedS[9]},   {kRedP[10], kRedS[10]}, {kRedP[11], kRedS[11]},
+    {kRedP[12], kRedS[12]}, {kRedP[13], kRedS[13]}, {kRedP[14], kRedS[14]}, {kRedP[15], kRedS[15]}};
+
+__host__ __device__ constexpr bool kept(int g) { return exp_of(g).c < 2; }
+
+// position of a kept multi-index among the kept ones of [lo, g)
+__host__ __device__ constexpr int kept_slot(int lo, int g)
 {
-    if constexpr (ord_of(A) + ord_of(B) <= 3) {
-        constexpr int S = sum_idx(A, B);
-        L[A] = __builtin_fma(q[B], G[S], L[A]);
+    int n = 0;
+    for (int h = lo; h < g; ++h) n += kept(h) ? 1 : 0;
+    return n;
+}
+
+constexpr bool check_reduction()
+{
+    for (int b = 0; b < kNRed; ++b) {
+        if (kRedS[b] < 0) continue;
+        // the eliminated component is the primary one with an xx (or yy) traded for zz
+        const Exp3 p = exp_of(kRedP[b]), q = exp_of(kRedS[b]);
+        const bool via_x = p.a >= 2 && q.a == p.a - 2 && q.b == p.b && q.c == p.c + 2;
+        const bool via_y = p.b >= 2 && q.b == p.b - 2 && q.a == p.a && q.c == p.c + 2;
+        if (!via_x && !via_y) return false;
+    }
+    return kept_slot(0, 20) == 16 && kept_slot(1, 35) == 24;
+}
+static_assert(check_reduction(), "trace reduction tables");
+
+// truncation rules: acc over outputs g (range [LO, LO + N)) and reduced sources b
+enum Trunc : int { TRUNC3 = 0, TRUNC4 = 1, EXACT4 = 2 };
+
+__host__ __device__ constexpr bool allowed(int rule, int og, int ob)
+{
+    return rule == TRUNC3 ? og + ob <= 3 : (rule == TRUNC4 ? og + ob <= 4 : og + ob == 4);
+}
+
+template <int LO, int RULE, int G_, int B>
+__device__ __forceinline__ void term_red(double* acc, const double* r, const double* G)
+{
+    if constexpr (kept(G_) && allowed(RULE, ord_of(G_), ord_of(kRedP[B]))) {
+        constexpr int slot = kept_slot(LO, G_);
+        constexpr int S = sum_idx(G_, kRedP[B]);
+        acc[slot] = __builtin_fma(r[B], G[S], acc[slot]);
     }
 }
-template <int A, int... B>
-__device__ __forceinline__ void row_fwd(double* L, const double* q, const double* G,
+template <int LO, int RULE, int G_, int... B>
+__device__ __forceinline__ void row_red(double* acc, const double* r, const double* G,
                                         std::integer_sequence<int, B...>)
 {
-    (term_fwd<A, B>(L, q, G), ...);
+    (term_red<LO, RULE, G_, B>(acc, r, G), ...);
 }
-template <int... A>
-__device__ __forceinline__ void contract_fwd(double* L, const double* q, const double* G,
-                                             std::integer_sequence<int, A...>)
+// acc[kept slot of g] += sum_b r[b] G[g + kRedP[b]] for g in [LO, LO + sizeof...(I))
+template <int LO, int RULE, int... I>
+__device__ __forceinline__ void contract_red(double* acc, const double* r, const double* G,
+                                             std::integer_sequence<int, I...>)
 {
-    (row_fwd<A>(L, q, G, std::make_integer_sequence<int, 20>{}), ...);
+    (row_red<LO, RULE, LO + I>(acc, r, G, std::make_integer_sequence<int, kNRed>{}), ...);
 }
 
-// E[C-1] += sum_{A: |A| + |C| = 4} q[A] G[A+C]   for 1 <= |C| <= 4 (111 FMAs)
-template <int C, int A>
-__device__ __forceinline__ void term_e(double* E, const double* q, const double* G)
+// full[g - LO] for g in [LO, LO + sizeof...(I)) from the kept accumulators;
+// outputs with z exponent >= 2 are rebuilt in index order (their two
+// partners always come earlier in graded-lex order).
+template <int LO, int G_>
+__device__ __forceinline__ void expand_one(const double* acc, double* full)
 {
-    if constexpr (ord_of(A) + ord_of(C) == 4) {
-        constexpr int S = sum_idx(A, C);
-        E[C - 1] = __builtin_fma(q[A], G[S], E[C - 1]);
+    if constexpr (kept(G_)) {
+        constexpr int slot = kept_slot(LO, G_);
+        full[G_ - LO] = acc[slot];
+    } else {
+        constexpr Exp3 e = exp_of(G_);
+        constexpr int gx = idx_of(e.a + 2, e.b, e.c - 2);
+        constexpr int gy = idx_of(e.a, e.b + 2, e.c - 2);
+        full[G_ - LO] = -(full[gx - LO] + full[gy - LO]);
     }
 }
-template <int C, int... A>
-__device__ __forceinline__ void row_e(double* E, const double* q, const double* G,
-                                      std::integer_sequence<int, A...>)
+template <int LO, int... I>
+__device__ __forceinline__ void expand(const double* acc, double* full, std::integer_sequence<int, I...>)
 {
-    (term_e<C + 1, A>(E, q, G), ...);
-}
-template <int... C>
-__device__ __forceinline__ void contract_e(double* E, const double* q, const double* G,
-                                           std::integer_sequence<int, C...>)
-{
-    (row_e<C>(E, q, G, std::make_integer_sequence<int, 20>{}), ...);
+    (expand_one<LO, LO + I>(acc, full), ...);
 }
 
-// Adjoint epilogue: with C_g = F_g + E_g (1 <= |g| <= 3) and C_g = E_g
-// (|g| = 4), the position gradient is gX_k = sum_a c_a C_{a+e_k}, where c_a is
-// the target's weight w_a (target role) or M_a / a! (source role).
+// Adjoint epilogue: with C_g (g = 1..34, stored at C[g - 1]) the derivative
+// sums of orders 1..4 -- L'_g for the target role, F_g + E_g (E_g alone for
+// |g| = 4) for the source role -- the position gradient is
+// gX_k = sum_a c_a C_{a+e_k}, where c_a is the target's weight w_a (target
+// role) or M_a / a! (source role).
 template <int A, int K>
-__device__ __forceinline__ double c_term(const double* F, const double* E)
+__device__ __forceinline__ double c_term(const double* C)
 {
     constexpr int g = sum_idx(A, K);
-    if constexpr (g < 20)
-        return F[g] + E[g - 1];
-    else
-        return E[g - 1];
+    return C[g - 1];
 }
 template <int... A>
-__device__ __forceinline__ void grad_x(const double* c, const double* F, const double* E,
-                                       double* gx, std::integer_sequence<int, A...>)
+__device__ __forceinline__ void grad_x(const double* c, const double* C, double* gx,
+                                       std::integer_sequence<int, A...>)
 {
-    ((gx[0] = __builtin_fma(c[A], c_term<A, 1>(F, E), gx[0]),
-      gx[1] = __builtin_fma(c[A], c_term<A, 2>(F, E), gx[1]),
-      gx[2] = __builtin_fma(c[A], c_term<A, 3>(F, E), gx[2])),
+    ((gx[0] = __builtin_fma(c[A], c_term<A, 1>(C), gx[0]),
+      gx[1] = __builtin_fma(c[A], c_term<A, 2>(C), gx[1]),
+      gx[2] = __builtin_fma(c[A], c_term<A, 3>(C), gx[2])),
      ...);
+}
+// C_g = F_g + E_g for 1 <= |g| <= 3, E_g for |g| = 4 (g = I + 1)
+template <int... I>
+__device__ __forceinline__ void combine_fe(const double* F, const double* E, double* C,
+                                           std::integer_sequence<int, I...>)
+{
+    ((C[I] = (I + 1 < 20) ? F[(I + 1) % 20] + E[I] : E[I]), ...);
 }
 template <int A>
 __device__ __forceinline__ double inv_fact_c()
@@ -481,10 +544,16 @@ struct KParams {
 template <int MODE>
 struct ModeTraits {
     static constexpr bool halo = (MODE == MODE_MONO_HALO || MODE == MODE_FWD_HALO);
-    static constexpr int nq = (MODE == MODE_MONO_HALO) ? 1 : 20;  // staged source moments
-    static constexpr int nc = nq + 3;                              // + centre of mass
+    // staged source components: the mass, or the 16 trace-reduced moments
+    static constexpr int nq = (MODE == MODE_MONO_HALO) ? 1 : kNRed;
+    static constexpr int nc = nq + 3;  // + centre of mass
     static constexpr bool adjoint = (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE);
-    static constexpr int nacc = adjoint ? 54 : 20;
+    // accumulators: monopole 20; forward 16 kept of 20; target-role adjoint
+    // 24 kept of the 34 orders 1..4; source-role adjoint 16 + 24
+    static constexpr int nacc = (MODE == MODE_MONO_HALO)  ? 20
+                                : (MODE == MODE_B1_STORE) ? 24
+                                : (MODE == MODE_B2_STORE) ? 40
+                                                          : 16;
 };
 
 // LDS plane layout: cell-major, Layout::stride doubles per cell -- the
@@ -520,27 +589,38 @@ constexpr int lds_doubles()
 // (valid memory) and replaced by zero moments and a far centre.
 template <int MODE>
 struct Chunk {
-    const double* src;  // component base, already offset to the cell
-    double scale, add, fill;
+    const double* src;   // first operand, already offset to the cell
+    const double* src2;  // second operand (the same address when unused)
+    double a1, a2;       // value = a1 * src + a2 * src2 (+ add)
+    double add, fill;
     bool present;
 };
 
+// Component c of the staged plane: 0..2 centre of mass, 3.. source value b =
+// c - 3 -- the mass (monopole) or trace-reduced moment b, i.e. the
+// difference of two scaled moments.
 template <int MODE>
 __device__ __forceinline__ Chunk<MODE> chunk_of(const KParams& p, const int4* rel, int zs, int u,
                                                 int lane)
 {
     using T = ModeTraits<MODE>;
-    const int c = u / 9;  // 0..2 centre, 3.. sources
+    const int c = u / 9;
     const int bxy = u - 9 * c;
     const int by = bxy / 3, bx = bxy - 3 * by;
     const bool isx = c < 3;
-    const int cm = isx ? 0 : c - 3;
+    const int rb = isx ? 0 : c - 3;
+    const int cP = c_red_src[rb][0];
+    const int cS = c_red_src[rb][1];
+    const int cS2 = cS >= 0 ? cS : cP;
     const int cx = isx ? c : 0;
+    const double* sc = (MODE == MODE_B2_STORE) ? c_scale_rev : c_scale_fwd;
     Chunk<MODE> ch;
+    long off, stride_c;
+    const double* base;
     if constexpr (T::halo) {
-        const long h = (long)zs * kPlane + (by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7);
-        ch.src = (isx ? p.pos + (long)cx * kHalo3 : p.mom + (long)cm * kHalo3) + h;
-        ch.scale = isx ? 1.0 : c_scale_fwd[cm];
+        off = (long)zs * kPlane + (by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7);
+        stride_c = kHalo3;
+        base = isx ? p.pos : p.mom;
         ch.add = 0.0;
         ch.fill = 0.0;
         ch.present = true;
@@ -548,13 +628,16 @@ __device__ __forceinline__ Chunk<MODE> chunk_of(const KParams& p, const int4* re
         const int4 rr = rel[9 * (zs >> 3) + bxy];  // uniform address: scalar load
         ch.present = rr.x >= 0;
         const long blk = ch.present ? (isx ? rr.y : rr.x) : 0;
-        const long lidx = blk * kSub3 + 64 * (zs & 7) + lane;
-        ch.src = (isx ? p.pos + (long)cx * p.pos_stride : p.mom + (long)cm * p.mom_stride) + lidx;
-        const double sc = (MODE == MODE_B2_STORE) ? c_scale_rev[cm] : c_scale_fwd[cm];
-        ch.scale = isx ? 1.0 : sc;
+        off = blk * kSub3 + 64 * (zs & 7) + lane;
+        stride_c = isx ? p.pos_stride : p.mom_stride;
+        base = isx ? p.pos : p.mom;
         ch.add = isx ? (double)(int)(int8_t)((rr.z >> (8 * cx)) & 0xff) * p.period[cx] : 0.0;
         ch.fill = isx ? kFar : 0.0;
     }
+    ch.src = base + (long)(isx ? cx : cP) * stride_c + off;
+    ch.src2 = base + (long)(isx ? cx : cS2) * stride_c + off;
+    ch.a1 = isx ? 1.0 : sc[cP];
+    ch.a2 = (isx || cS < 0) ? 0.0 : -sc[cS2];
     return ch;
 }
 
@@ -575,23 +658,31 @@ __device__ __forceinline__ void stage_plane(const KParams& p, const int4* rel, i
     constexpr int NCH = 9 * T::nc;   // chunks per plane
     constexpr int FULL = NCH / NW;   // chunks every wavefront has
     const bool tail = wave + FULL * NW < NCH;
-    double raw[FULL + 1];
+    double raw[FULL + 1], raw2[FULL + 1];
 #pragma unroll
-    for (int k = 0; k < FULL; ++k) raw[k] = *chunk_of<MODE>(p, rel, zs, wave + k * NW, lane).src;
-    raw[FULL] = 0.0;
-    if (tail) raw[FULL] = *chunk_of<MODE>(p, rel, zs, wave + FULL * NW, lane).src;
+    for (int k = 0; k < FULL; ++k) {
+        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, wave + k * NW, lane);
+        raw[k] = *ch.src;
+        raw2[k] = *ch.src2;
+    }
+    raw[FULL] = raw2[FULL] = 0.0;
+    if (tail) {
+        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, wave + FULL * NW, lane);
+        raw[FULL] = *ch.src;
+        raw2[FULL] = *ch.src2;
+    }
 #pragma unroll
     for (int k = 0; k < FULL; ++k) {
         const int u = wave + k * NW;
         const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
-        lds[chunk_lds_index<MODE>(u, lane)] =
-            ch.present ? __builtin_fma(raw[k], ch.scale, ch.add) : ch.fill;
+        const double v = __builtin_fma(raw2[k], ch.a2, raw[k] * ch.a1) + ch.add;
+        lds[chunk_lds_index<MODE>(u, lane)] = ch.present ? v : ch.fill;
     }
     if (tail) {
         const int u = wave + FULL * NW;
         const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
-        lds[chunk_lds_index<MODE>(u, lane)] =
-            ch.present ? __builtin_fma(raw[FULL], ch.scale, ch.add) : ch.fill;
+        const double v = __builtin_fma(raw2[FULL], ch.a2, raw[FULL] * ch.a1) + ch.add;
+        lds[chunk_lds_index<MODE>(u, lane)] = ch.present ? v : ch.fill;
     }
 }
 
@@ -601,7 +692,6 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     using T = ModeTraits<MODE>;
     using Lay = Layout<MODE>;
     static_assert(NW == 8 || NW == 16, "8 or 16 wavefronts");
-    static_assert(!(T::adjoint && NW != 8), "adjoint passes use 8 wavefronts");
     __shared__ double lds[lds_doubles<MODE, NW>()];
 
     const int tid = threadIdx.x;
@@ -680,14 +770,21 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
 #pragma unroll
                         for (int a = 0; a < 20; ++a) acc[a] = __builtin_fma(q[0], G[a], acc[a]);
                     } else if constexpr (!T::adjoint) {
+                        // L_a, |a| + |b| <= 3
                         double G[20];
                         green<3>(rx, ry, rz, G);
-                        contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
-                    } else {
+                        contract_red<0, TRUNC3>(acc, q, G, std::make_integer_sequence<int, 20>{});
+                    } else if constexpr (MODE == MODE_B1_STORE) {
+                        // L'_g, 1 <= |g| <= 4, |g| + |b| <= 4
                         double G[35];
                         green<4>(rx, ry, rz, G);
-                        contract_fwd(acc, q, G, std::make_integer_sequence<int, 20>{});
-                        contract_e(acc + 20, q, G, std::make_integer_sequence<int, 34>{});
+                        contract_red<1, TRUNC4>(acc, q, G, std::make_integer_sequence<int, 34>{});
+                    } else {
+                        // F_d (|d| + |a| <= 3) and E_d (|d| + |a| = 4, |d| >= 1)
+                        double G[35];
+                        green<4>(rx, ry, rz, G);
+                        contract_red<0, TRUNC3>(acc, q, G, std::make_integer_sequence<int, 20>{});
+                        contract_red<1, EXACT4>(acc + 16, q, G, std::make_integer_sequence<int, 34>{});
                     }
                 }
             }
@@ -695,29 +792,51 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     }
 
     // ---------------- epilogues ----------------
-    if constexpr (!T::adjoint) {
-        if constexpr (NW == 16) {
+    if constexpr (NW == 16) {
+        // the two wavefronts of a target plane add their partial sums, through
+        // LDS in rounds of at most 20 components
+#pragma unroll
+        for (int a0 = 0; a0 < T::nacc; a0 += 20) {
             __syncthreads();
             if (half == 1) {
 #pragma unroll
-                for (int a = 0; a < 20; ++a) lds[a * kSub3 + cell] = acc[a];
+                for (int a = a0; a < T::nacc && a < a0 + 20; ++a) lds[(a - a0) * kSub3 + cell] = acc[a];
             }
             __syncthreads();
-            if (half == 1) return;
+            if (half == 0) {
 #pragma unroll
-            for (int a = 0; a < 20; ++a) acc[a] += lds[a * kSub3 + cell];
+                for (int a = a0; a < T::nacc && a < a0 + 20; ++a) acc[a] += lds[(a - a0) * kSub3 + cell];
+            }
+        }
+        if (half == 1) return;
+    }
+    if constexpr (!T::adjoint) {
+        double L[20];
+        if constexpr (MODE == MODE_MONO_HALO) {
+#pragma unroll
+            for (int a = 0; a < 20; ++a) L[a] = acc[a];
+        } else {
+            expand<0>(acc, L, std::make_integer_sequence<int, 20>{});
         }
         if constexpr (T::halo) {
 #pragma unroll
-            for (int a = 0; a < 20; ++a) p.out0[a * kSub3 + cell] = acc[a];
+            for (int a = 0; a < 20; ++a) p.out0[a * kSub3 + cell] = L[a];
         } else {
             const long b = p.out_blk ? p.out_blk[owner] : owner;
 #pragma unroll
-            for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + b * kSub3 + cell] = acc[a];
+            for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + b * kSub3 + cell] = L[a];
         }
     } else {
-        const double* F = acc;
-        const double* E = acc + 20;
+        double C[34];
+        double F[20];
+        if constexpr (MODE == MODE_B1_STORE) {
+            expand<1>(acc, C, std::make_integer_sequence<int, 34>{});
+        } else {
+            double E[34];
+            expand<0>(acc, F, std::make_integer_sequence<int, 20>{});
+            expand<1>(acc + 16, E, std::make_integer_sequence<int, 34>{});
+            combine_fe(F, E, C, std::make_integer_sequence<int, 34>{});
+        }
         const long ab = (long)owner * kSub3 + cell;
         double c[20];
 #pragma unroll
@@ -725,16 +844,13 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         if constexpr (MODE == MODE_B2_STORE)
             scale_inv_fact(c, std::make_integer_sequence<int, 20>{});  // M_b / b!
         double gx[3] = {0.0, 0.0, 0.0};
-        grad_x(c, F, E, gx, std::make_integer_sequence<int, 20>{});
+        grad_x(c, C, gx, std::make_integer_sequence<int, 20>{});
         const long b = p.out_blk ? p.out_blk[owner] : owner;
         const long ob = b * kSub3 + cell;
         if constexpr (MODE == MODE_B2_STORE) {
-            double gm[20];
+            scale_inv_fact(F, std::make_integer_sequence<int, 20>{});  // gM_b = F_b / b!
 #pragma unroll
-            for (int a = 0; a < 20; ++a) gm[a] = F[a];
-            scale_inv_fact(gm, std::make_integer_sequence<int, 20>{});  // F_b / b!
-#pragma unroll
-            for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = gm[a];
+            for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = F[a];
 #pragma unroll
             for (int k = 0; k < 3; ++k) p.out1[k * p.out_stride + ob] = gx[k];
         } else {
@@ -880,8 +996,9 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
 int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
                 double* gM, double* gcom, int sched, hipStream_t stream)
 {
-    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_bwd ? plan->tuned_bwd : OT_FMM_SCHED_W8;
-    if (sched != OT_FMM_SCHED_W8) return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_bwd ? plan->tuned_bwd : OT_FMM_SCHED_W16;
+    if (sched != OT_FMM_SCHED_W8 && sched != OT_FMM_SCHED_W16)
+        return fail(OT_FMM_EINVAL, "unknown backward schedule");
     const long NS = (long)plan->S * kSub3, NT = (long)plan->T * kSub3;
     // source role: owners are store sub-grids, sources the target cells that see them
     KParams b2{};
@@ -916,6 +1033,9 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b1.out_stride = NS;
     b1.out_blk = plan->d_tgt;
     for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
+    // the source-role pass keeps 8 wavefronts (its 40 accumulators do not fit
+    // the register budget of 16); the target-role pass follows the schedule
+    if (sched == OT_FMM_SCHED_W16) return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, stream);
     return launch_timed<MODE_B1_STORE, 8>(plan, 2, b1, plan->T, stream);
 }
 
@@ -1148,8 +1268,7 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     if (gM == M || gM == gL || gcom == com || (const double*)gcom == gL || (const double*)gM == com)
         return fail(OT_FMM_EINVAL, "outputs alias inputs");
-    if (sched != OT_FMM_SCHED_AUTO && sched != OT_FMM_SCHED_W8)
-        return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    if (sched < 0 || sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown backward schedule");
     return bwd_batched(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
 }
 
@@ -1191,10 +1310,18 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
             best_f = cand;
         }
     }
-    int best_b = OT_FMM_SCHED_W8;
+    int best_b = OT_FMM_SCHED_W16;
     if (!rc && with_bwd) {
-        float ms = 0.0f;
-        rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, OT_FMM_SCHED_W8, s); }, &ms);
+        best_ms = 3.0e38f;
+        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16}) {
+            float ms = 0.0f;
+            rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, cand, s); }, &ms);
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_b = cand;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1219,7 +1346,7 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
     if (fwd_sched < 0 || fwd_sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
-    if (with_bwd && bwd_sched != OT_FMM_SCHED_AUTO && bwd_sched != OT_FMM_SCHED_W8)
+    if (with_bwd && (bwd_sched < 0 || bwd_sched > OT_FMM_SCHED_W16))
         return fail(OT_FMM_EINVAL, "unknown backward schedule");
     hipStream_t cs;
     OT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

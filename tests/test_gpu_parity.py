@@ -126,14 +126,15 @@ def _small_adjoint_case():
     return batch, M, X
 
 
-def test_backward_small_open(ot):
+@pytest.mark.parametrize("sched", [1, 2])
+def test_backward_small_open(ot, sched):
     batch, M, X = _small_adjoint_case()
     w = synthetic.weights(batch["T"], 42)
     gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w)
     plan = ot.Plan.from_batch(batch)
     gM = _empty(20, 27 * 512)
     gX = _empty(3, 27 * 512)
-    plan.multipole_backward(_dev(M), _dev(X), _dev(w), gM, gX)
+    plan.multipole_backward(_dev(M), _dev(X), _dev(w), gM, gX, sched=sched)
     print("gM worst", assert_parity(_host(gM), gM_ref, TOL, what="gM"))
     print("gX worst", assert_parity(_host(gX), gX_ref, TOL, what="gX"))
 
@@ -224,7 +225,7 @@ def test_autotune_choices_are_valid_and_exact(ot):
     Md, Xd = _dev(M), _dev(X)
     L = _empty(20, batch["T"] * 512)
     f, b = plan.autotune(Md, Xd, L)
-    assert f in (1, 2) and b == 1
+    assert f in (1, 2) and b in (1, 2)
     plan.multipole_batched(Md, Xd, L)   # AUTO -> tuned
     ref = oracle.batched_forward(batch, M, X, tsel=[0, 5, 26])
     got = _host(L).reshape(20, 27, 512)[:, [0, 5, 26]].reshape(20, -1)
