@@ -48,6 +48,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel, sched, n):
+    """HBM-side bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+    copy of known size) from the committed counter summary, when it was taken
+    on this kernel source and this workload; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_32768_subgrids.json")
+    src = os.path.join(ROOT, "paper_2303_08058_amd", "csrc", "ot_fmm.hip")
+    if n != 32 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    key = {"forward": "forward", "adjoint_source": "adjoint_source",
+           "adjoint_target": "adjoint_target"}[kernel]
+    key += "_w16" if (sched == 2 and kernel != "adjoint_source") else "_w8"
+    k = rec["kernels"].get(key)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +154,7 @@ def main():
         log("kernel %-15s %.3f ms  %.2f TFLOP/s" % (k, mean, kernels[k]["tflops"]))
     dom = max(kernels, key=lambda k: kernels[k]["mean_ms"])
     achieved = kernels[dom]["tflops"]
+    traffic = measured_traffic(dom, fs if dom == "forward" else bs, args.n)
     fwd_pairs_s = pairs / (kernels["forward"]["mean_ms"] * 1e-3)
     sum_ms = sum(v["mean_ms"] for v in kernels.values())
     fwdbwd_flops = pairs * sum(FLOP_PER_PAIR.values()) / (ms_per_step * 1e-3) / 1e12
@@ -181,7 +201,10 @@ def main():
         },
         "roofline": {
             "bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM side, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "flop_basis": "algorithmic FP64 ops per cell pair of the plain formulas (FMA = 2, "
+                          "rsqrt = 1) x exact pairs per launch",
         },
         "kernels": kernels,
         "fwd_bwd_tflops": round(fwdbwd_flops, 3),
