@@ -287,10 +287,15 @@ def per_subgrid_comparison(n, ot, synthetic, np, torch, dev):
         res["speedup_vs_%dstream" % nstreams] = round(ms / batched_ms, 2)
         log("per-sub-grid launches on %2d stream(s): %.1f ms (%.1fx slower)"
             % (nstreams, ms, ms / batched_ms))
-    # same numbers as the batched launch (the missing cells add exact zeros)
+    # same numbers as the batched launch up to summation order (the missing
+    # cells add exact zeros): per target and output order, max |diff| / max |L|
     Lb = L.reshape(20, T, 512).permute(1, 0, 2)
-    scale = Lb.abs().amax(dim=2, keepdim=True)
-    res["max_rel_diff_vs_batched"] = float(((Lh - Lb).abs() / scale).max())
+    worst = 0.0
+    for g in ([0], [1, 2, 3], list(range(4, 10)), list(range(10, 20))):
+        d = (Lh[:, g] - Lb[:, g]).abs().amax(dim=(1, 2))
+        sc = Lb[:, g].abs().amax(dim=(1, 2))
+        worst = max(worst, float((d / sc).max()))
+    res["max_rel_diff_vs_batched"] = worst
     del Mh, Xh, Lh
     torch.cuda.empty_cache()
     return res

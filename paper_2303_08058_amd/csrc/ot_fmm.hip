@@ -76,6 +76,7 @@ int hip_fail(hipError_t e, const char* what)
 // ---------------------------------------------------------------------------
 // Geometry constants
 // ---------------------------------------------------------------------------
+constexpr int kSub = 8;
 constexpr int kSub3 = 512;
 constexpr int kHalo = 24;
 constexpr int kPlane = kHalo * kHalo;   // 576 cells per halo z-plane
@@ -569,16 +570,19 @@ struct Layout {
     static constexpr int stride = (nvec % 2 == 1) ? 2 * nvec : 2 * nvec + 2;  // doubles per cell
 };
 
-template <int MODE, int NW>
+template <int MODE, int NW, bool SPLIT>
 constexpr int lds_doubles()
 {
     constexpr int plane = Layout<MODE>::stride * kPlane;
-    constexpr int merge = (NW == 16) ? 20 * kSub3 : 0;
+    constexpr int merge = SPLIT ? NW * ModeTraits<MODE>::nacc * 64 : ((NW == 16) ? 20 * kSub3 : 0);
     return plane > merge ? plane : merge;
 }
 
 // Staging of one halo z-plane: every global load of the calling thread is
-// issued first, then the values are scaled and written into the LDS plane.
+// issued first (stage_load), then the values are scaled and written into the
+// LDS plane (stage_store), back to back between two barriers. (Issuing the
+// next plane's loads before the barrier, to overlap the wait, was measured
+// slower: the held registers spill.)
 // Work unit ("chunk"): one component of one 8x8-cell block of the plane (one
 // of the 3x3 neighbour sub-grids crossing it); lane l takes cell
 // (l % 8, l / 8) of the block, so a wavefront reads 512 contiguous bytes.
@@ -651,56 +655,80 @@ __device__ __forceinline__ int chunk_lds_index(int u, int lane)
 }
 
 template <int MODE, int NW>
-__device__ __forceinline__ void stage_plane(const KParams& p, const int4* rel, int zs, int wave,
-                                            int lane, double* lds)
-{
-    using T = ModeTraits<MODE>;
-    constexpr int NCH = 9 * T::nc;   // chunks per plane
-    constexpr int FULL = NCH / NW;   // chunks every wavefront has
-    const bool tail = wave + FULL * NW < NCH;
+struct PlaneLoad {
+    static constexpr int NCH = 9 * ModeTraits<MODE>::nc;  // chunks per plane
+    static constexpr int FULL = NCH / NW;                 // chunks every wavefront has
     double raw[FULL + 1], raw2[FULL + 1];
+};
+
+// Phase 1: issue every global load of the wavefront's chunks of plane zs.
+template <int MODE, int NW>
+__device__ __forceinline__ void stage_load(PlaneLoad<MODE, NW>& pl, const KParams& p,
+                                           const int4* rel, int zs, int wave, int lane)
+{
+    constexpr int NCH = PlaneLoad<MODE, NW>::NCH;
+    constexpr int FULL = PlaneLoad<MODE, NW>::FULL;
 #pragma unroll
     for (int k = 0; k < FULL; ++k) {
         const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, wave + k * NW, lane);
-        raw[k] = *ch.src;
-        raw2[k] = *ch.src2;
+        pl.raw[k] = *ch.src;
+        pl.raw2[k] = *ch.src2;
     }
-    raw[FULL] = raw2[FULL] = 0.0;
-    if (tail) {
+    pl.raw[FULL] = pl.raw2[FULL] = 0.0;
+    if (wave + FULL * NW < NCH) {
         const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, wave + FULL * NW, lane);
-        raw[FULL] = *ch.src;
-        raw2[FULL] = *ch.src2;
+        pl.raw[FULL] = *ch.src;
+        pl.raw2[FULL] = *ch.src2;
     }
+}
+
+// Phase 2: scale / combine / shift the loaded values and write the LDS plane.
+template <int MODE, int NW>
+__device__ __forceinline__ void stage_store(const PlaneLoad<MODE, NW>& pl, const KParams& p,
+                                            const int4* rel, int zs, int wave, int lane,
+                                            double* lds)
+{
+    constexpr int NCH = PlaneLoad<MODE, NW>::NCH;
+    constexpr int FULL = PlaneLoad<MODE, NW>::FULL;
 #pragma unroll
     for (int k = 0; k < FULL; ++k) {
         const int u = wave + k * NW;
         const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
-        const double v = __builtin_fma(raw2[k], ch.a2, raw[k] * ch.a1) + ch.add;
+        const double v = __builtin_fma(pl.raw2[k], ch.a2, pl.raw[k] * ch.a1) + ch.add;
         lds[chunk_lds_index<MODE>(u, lane)] = ch.present ? v : ch.fill;
     }
-    if (tail) {
+    if (wave + FULL * NW < NCH) {
         const int u = wave + FULL * NW;
         const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
-        const double v = __builtin_fma(raw2[FULL], ch.a2, raw[FULL] * ch.a1) + ch.add;
+        const double v = __builtin_fma(pl.raw2[FULL], ch.a2, pl.raw[FULL] * ch.a1) + ch.add;
         lds[chunk_lds_index<MODE>(u, lane)] = ch.present ? v : ch.fill;
     }
 }
 
-template <int MODE, int NW>
+// SPLIT (single-block forms only): one work-group per target z-plane of the
+// block; its NW wavefronts share the plane's 64 cells and take the stencil
+// rows round-robin; only the 19 source planes within reach are staged, and the
+// partial sums are added in a fixed order at the end.
+template <int MODE, int NW, bool SPLIT>
 __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
 {
     using T = ModeTraits<MODE>;
     using Lay = Layout<MODE>;
     static_assert(NW == 8 || NW == 16, "8 or 16 wavefronts");
-    __shared__ double lds[lds_doubles<MODE, NW>()];
+    static_assert(!SPLIT || (T::halo && NW == 8), "plane split: single-block forms, 8 wavefronts");
+    __shared__ double lds[lds_doubles<MODE, NW, SPLIT>()];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int owner = p.order ? p.order[blockIdx.x] : (int)blockIdx.x;
+    const int owner = SPLIT ? 0 : (p.order ? p.order[blockIdx.x] : (int)blockIdx.x);
     const int4* s_rel = T::halo ? nullptr : p.rel + (long)owner * 27;  // this owner's relations
-    const int zt = (NW == 16) ? (wave >> 1) : wave;
-    const int half = (NW == 16) ? (wave & 1) : 0;
+    // With 8 wavefronts (wave w on SIMD w % 4) the target planes are paired per
+    // SIMD as (0,4) (1,6) (2,5) (3,7): the pairing whose summed per-plane work
+    // varies least from one staged plane to the next.
+    const int zt = SPLIT ? (int)blockIdx.x
+                         : ((NW == 16) ? (wave >> 1) : (wave == 5 ? 6 : (wave == 6 ? 5 : wave)));
+    const int half = (!SPLIT && NW == 16) ? (wave & 1) : 0;
     const int xt = lane & 7, yt = lane >> 3;
     const int pz = zt & 1;
     const int cell = xt + 8 * yt + 64 * zt;
@@ -732,21 +760,32 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     const int step_y = sgy * kHalo * cs;
     const double2* lds2 = reinterpret_cast<const double2*>(lds);
 
-    for (int zs = 0; zs < kHalo; ++zs) {
+    const int zs_begin = SPLIT ? (8 + zt - kReach > 0 ? 8 + zt - kReach : 0) : 0;
+    const int zs_end = SPLIT ? (8 + zt + kReach + 1 < kHalo ? 8 + zt + kReach + 1 : kHalo) : kHalo;
+    // the next plane's loads are issued as soon as a wavefront is done with
+    // the current one, so they overlap the barrier wait
+    for (int zs = zs_begin; zs < zs_end; ++zs) {
         __syncthreads();
-        stage_plane<MODE, NW>(p, s_rel, zs, wave, lane, lds);
+        {
+            PlaneLoad<MODE, NW> pl;
+            stage_load<MODE, NW>(pl, p, s_rel, zs, wave, lane);
+            stage_store<MODE, NW>(pl, p, s_rel, zs, wave, lane, lds);
+        }
         __syncthreads();
         const int dz = zs - (8 + zt);
         if (dz >= -kReach && dz <= kReach) {
             const int* rg = c_stencil.range[pz][dz + kReach];
-            int r0 = rg[0], r1 = rg[2];
-            if (NW == 16) {
+            int r0 = rg[0], r1 = rg[2], rstep = 1;
+            if (SPLIT) {
+                r0 += wave;
+                rstep = NW;
+            } else if (NW == 16) {
                 if (half == 0)
                     r1 = rg[1];
                 else
                     r0 = rg[1];
             }
-            for (int r = r0; r < r1; ++r) {
+            for (int r = r0; r < r1; r += rstep) {
                 const uint32_t w = c_stencil.rows[pz][r];
                 const int dy = (int)(int8_t)(w & 0xff);
                 const int dx0 = (int)(int8_t)((w >> 8) & 0xff);
@@ -792,7 +831,20 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     }
 
     // ---------------- epilogues ----------------
-    if constexpr (NW == 16) {
+    if constexpr (SPLIT) {
+        // partial sums of the plane's wavefronts, added by wavefront 0 in order
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < T::nacc; ++a) lds[(wave * T::nacc + a) * 64 + lane] = acc[a];
+        __syncthreads();
+        if (wave != 0) return;
+#pragma unroll
+        for (int a = 0; a < T::nacc; ++a) {
+            double v = lds[a * 64 + lane];
+            for (int w = 1; w < NW; ++w) v += lds[(w * T::nacc + a) * 64 + lane];
+            acc[a] = v;
+        }
+    } else if constexpr (NW == 16) {
         // the two wavefronts of a target plane add their partial sums, through
         // LDS in rounds of at most 20 components
 #pragma unroll
@@ -895,11 +947,11 @@ int ensure_device()
 
 bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-template <int MODE, int NW>
+template <int MODE, int NW, bool SPLIT = false>
 int launch(const KParams& kp, int nblocks, hipStream_t stream)
 {
     if (nblocks <= 0) return OT_FMM_OK;
-    hipLaunchKernelGGL((k_interact<MODE, NW>), dim3(nblocks), dim3(NW * 64), 0, stream, kp);
+    hipLaunchKernelGGL((k_interact<MODE, NW, SPLIT>), dim3(nblocks), dim3(NW * 64), 0, stream, kp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return OT_FMM_OK;
@@ -1126,7 +1178,7 @@ int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stre
     kp.mom = mass;
     kp.pos = com;
     kp.out0 = L;
-    return launch<MODE_MONO_HALO, 16>(kp, 1, (hipStream_t)stream);
+    return launch<MODE_MONO_HALO, 8, true>(kp, kSub, (hipStream_t)stream);
 }
 
 int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream)
@@ -1140,7 +1192,7 @@ int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream
     kp.mom = M;
     kp.pos = com;
     kp.out0 = L;
-    return launch<MODE_FWD_HALO, 16>(kp, 1, (hipStream_t)stream);
+    return launch<MODE_FWD_HALO, 8, true>(kp, kSub, (hipStream_t)stream);
 }
 
 int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr,
