@@ -63,6 +63,12 @@ def _load():
     lib.orc_batched_forward_cs.restype = i
     lib.orc_batched_backward.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
     lib.orc_batched_backward.restype = i
+    lib.orc_m2m.argtypes = [i, i, P, P, P, P, i, P, P, i]
+    lib.orc_m2m.restype = i
+    lib.orc_l2l.argtypes = [i, i, P, P, P, P, P, i]
+    lib.orc_l2l.restype = i
+    lib.orc_evaluate.argtypes = [ctypes.c_long, P, P, P, P, i]
+    lib.orc_evaluate.restype = i
     _lib = lib
     return lib
 
@@ -180,3 +186,52 @@ def batched_backward(batch, M, X, gL, ssel=None, nthreads: int = 0):
     if rc:
         raise ValueError("orc_batched_backward rejected its arguments")
     return gM, gX
+
+
+# ---------------------------------------------------------------------------
+# tree passes around the interaction
+# ---------------------------------------------------------------------------
+def m2m(children, Mc, Xc, psel=None, nthreads: int = 0):
+    """Upward pass. children (Sp, 8) child node ids; Mc (20, Sc*512), Xc (3, Sc*512)
+    -> Mp (20, nsel*512), Xp (3, nsel*512) for the selected parent nodes."""
+    ch = _i32(children).reshape(-1, 8)
+    Sp = ch.shape[0]
+    Mc = _f64(Mc)
+    Xc = _f64(Xc)
+    Sc = Mc.shape[1] // SUB3
+    psel = np.arange(Sp, dtype=np.int32) if psel is None else _i32(psel)
+    Mp = np.zeros((NM, len(psel) * SUB3))
+    Xp = np.zeros((3, len(psel) * SUB3))
+    rc = _load().orc_m2m(Sp, Sc, _ptr(ch), _ptr(Mc), _ptr(Xc), _ptr(psel), len(psel), _ptr(Mp),
+                         _ptr(Xp), nthreads)
+    if rc:
+        raise ValueError("orc_m2m rejected its arguments")
+    return Mp, Xp
+
+
+def l2l(children, Lp, Xp, Xc, Lc, nthreads: int = 0):
+    """Downward pass: returns Lc + shifted parent expansions (Lc is not modified)."""
+    ch = _i32(children).reshape(-1, 8)
+    Lp = _f64(Lp)
+    Xp = _f64(Xp)
+    Xc = _f64(Xc)
+    out = np.array(Lc, dtype=np.float64, copy=True)
+    Sc = Xc.shape[1] // SUB3
+    rc = _load().orc_l2l(ch.shape[0], Sc, _ptr(ch), _ptr(Lp), _ptr(Xp), _ptr(Xc), _ptr(out),
+                         nthreads)
+    if rc:
+        raise ValueError("orc_l2l rejected its arguments")
+    return out
+
+
+def evaluate(M, L, nthreads: int = 0):
+    """Per-cell force F (3, N) and energy W (N,) from moments and local expansion."""
+    M = _f64(M)
+    L = _f64(L)
+    N = M.shape[1]
+    F = np.zeros((3, N))
+    W = np.zeros(N)
+    rc = _load().orc_evaluate(N, _ptr(M), _ptr(L), _ptr(F), _ptr(W), nthreads)
+    if rc:
+        raise ValueError("orc_evaluate rejected its arguments")
+    return F, W

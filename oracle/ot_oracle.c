@@ -520,3 +520,167 @@ int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Tree passes around the interaction (paper Sec. 2.1: the FMM works on the
+ * octree; Sec. 2.3: the gravity solver traverses the tree of sub-grids).
+ * A parent node p and its 8 child nodes children[p][o] (o = ox + 2 oy + 4 oz)
+ * hold 8^3 cells each; parent cell (X, Y, Z) covers the 2x2x2 child cells
+ * (2 (X % 4) + a, 2 (Y % 4) + b, 2 (Z % 4) + c) of child node o = (X/4, Y/4, Z/4).
+ * ------------------------------------------------------------------------- */
+static double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+/* d^e = d_x^e_x d_y^e_y d_z^e_z */
+static double mono(const double d[3], const int e[3])
+{
+    double v = 1.0;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < e[k]; ++i) v *= d[k];
+    return v;
+}
+
+static void parent_children_cells(int pc, int child_local[8], int *octant)
+{
+    int lp[3];
+    local_coords(pc, lp);
+    *octant = lp[0] / 4 + 2 * (lp[1] / 4) + 4 * (lp[2] / 4);
+    int n = 0;
+    for (int c = 0; c < 2; ++c)
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a) {
+                int l[3] = {2 * (lp[0] % 4) + a, 2 * (lp[1] % 4) + b, 2 * (lp[2] % 4) + c};
+                child_local[n++] = l[0] + SUB * l[1] + SUB * SUB * l[2];
+            }
+}
+
+/* Upward pass (M2M; P2M when the children are point masses): the parent
+ * cell's mass is the children's total, its centre the mass-weighted mean of
+ * the children's centres (their plain mean if the total mass is 0), and its
+ * raw moments about that centre follow from the children's by the binomial
+ * expansion of (x - X_p)^b = ((x - X_c) + (X_c - X_p))^b:
+ *   M_b(p) = sum_c sum_{g <= b} C(b, g) M_g(c) (X_c - X_p)^(b - g),
+ * C(b, g) = prod_k binom(b_k, g_k). Exact for |b| <= 3 (no truncation).
+ * Mc[20][Sc*512], Xc[3][Sc*512] -> Mp[20][nsel*512], Xp[3][nsel*512] over the
+ * selected parent nodes psel. */
+int orc_m2m(int Sp, int Sc, const int32_t *children, const double *Mc, const double *Xc,
+            const int32_t *psel, int nsel, double *Mp, double *Xp, int nthreads)
+{
+    init_tables();
+    if (Sp <= 0 || Sc <= 0 || !children) return -1;
+    for (int i = 0; i < Sp * 8; ++i)
+        if (children[i] < 0 || children[i] >= Sc) return -1;
+    for (int q = 0; q < nsel; ++q)
+        if (psel[q] < 0 || psel[q] >= Sp) return -1;
+    const size_t NC = (size_t)Sc * SUB3, NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int q = 0; q < nsel; ++q)
+        for (int pc = 0; pc < SUB3; ++pc) {
+            int p = psel[q], cl[8], o;
+            parent_children_cells(pc, cl, &o);
+            int blk = children[p * 8 + o];
+            double m = 0.0, mx[3] = {0, 0, 0}, gx[3] = {0, 0, 0};
+            for (int n = 0; n < 8; ++n) {
+                size_t j = (size_t)blk * SUB3 + cl[n];
+                m += Mc[j];
+                for (int k = 0; k < 3; ++k) {
+                    mx[k] += Mc[j] * Xc[k * NC + j];
+                    gx[k] += Xc[k * NC + j];
+                }
+            }
+            double X[3];
+            for (int k = 0; k < 3; ++k) X[k] = m > 0.0 ? mx[k] / m : gx[k] / 8.0;
+            double acc[NM] = {0};
+            for (int n = 0; n < 8; ++n) {
+                size_t j = (size_t)blk * SUB3 + cl[n];
+                double d[3] = {Xc[j] - X[0], Xc[NC + j] - X[1], Xc[2 * NC + j] - X[2]};
+                for (int b = 0; b < NM; ++b)
+                    for (int g = 0; g < NM; ++g) {
+                        int ok = 1, e[3];
+                        double c = 1.0;
+                        for (int k = 0; k < 3; ++k) {
+                            e[k] = g_exp[b][k] - g_exp[g][k];
+                            if (e[k] < 0) ok = 0;
+                            else c *= binom(g_exp[b][k], g_exp[g][k]);
+                        }
+                        if (!ok) continue;
+                        acc[b] += c * Mc[g * NC + j] * mono(d, e);
+                    }
+            }
+            for (int b = 0; b < NM; ++b) Mp[b * NO + (size_t)q * SUB3 + pc] = acc[b];
+            for (int k = 0; k < 3; ++k) Xp[k * NO + (size_t)q * SUB3 + pc] = X[k];
+        }
+    return 0;
+}
+
+/* Downward pass (L2L): the parent cell's local expansion
+ *   phi(x) = sum_a L_a(p) (x - X_p)^a / a!
+ * is re-expanded about each child cell's centre and kept to order 3:
+ *   L_a(c) += sum_{|g| <= 3 - |a|} L_{a+g}(p) (X_c - X_p)^g / g!
+ * (exact for the cubic phi). Lp[20][Sp*512], Xp[3][Sp*512], Xc[3][Sc*512];
+ * Lc[20][Sc*512] is accumulated into for every child node of a parent. */
+int orc_l2l(int Sp, int Sc, const int32_t *children, const double *Lp, const double *Xp,
+            const double *Xc, double *Lc, int nthreads)
+{
+    init_tables();
+    if (Sp <= 0 || Sc <= 0 || !children) return -1;
+    for (int i = 0; i < Sp * 8; ++i)
+        if (children[i] < 0 || children[i] >= Sc) return -1;
+    const size_t NC = (size_t)Sc * SUB3, NP = (size_t)Sp * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int p = 0; p < Sp; ++p)
+        for (int pc = 0; pc < SUB3; ++pc) {
+            int cl[8], o;
+            parent_children_cells(pc, cl, &o);
+            int blk = children[p * 8 + o];
+            size_t ip = (size_t)p * SUB3 + pc;
+            for (int n = 0; n < 8; ++n) {
+                size_t j = (size_t)blk * SUB3 + cl[n];
+                double d[3] = {Xc[j] - Xp[ip], Xc[NC + j] - Xp[NP + ip], Xc[2 * NC + j] - Xp[2 * NP + ip]};
+                for (int a = 0; a < NM; ++a) {
+                    double s = 0.0;
+                    for (int g = 0; g < NM; ++g) {
+                        if (order_of(a) + order_of(g) > 3) continue;
+                        s += Lp[sum_index(a, g) * NP + ip] * mono(d, g_exp[g]) /
+                             (factorial(g_exp[g][0]) * factorial(g_exp[g][1]) * factorial(g_exp[g][2]));
+                    }
+                    Lc[a * NC + j] += s;
+                }
+            }
+        }
+    return 0;
+}
+
+/* Local evaluation of a cell from its moments M (about its centre) and its
+ * local expansion L (about the same centre):
+ *   force      F_k = - sum_{|a| <= 2} M_a / a! L_{a+e_k}
+ *   energy     W   = 1/2 sum_{|a| <= 3} M_a / a! L_a
+ * (the integrals of -rho grad(phi) and rho phi / 2 over the cell's mass, with
+ * phi truncated at order 3). M, L [20][N] -> F[3][N], W[N]. */
+int orc_evaluate(long N, const double *M, const double *L, double *F, double *W, int nthreads)
+{
+    init_tables();
+    if (N <= 0) return -1;
+    int ek[3] = {index_of(1, 0, 0), index_of(0, 1, 0), index_of(0, 0, 1)};
+    set_threads(nthreads);
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < N; ++i) {
+        double f[3] = {0, 0, 0}, w = 0.0;
+        for (int a = 0; a < NM; ++a) {
+            double ma = M[a * N + i] /
+                        (factorial(g_exp[a][0]) * factorial(g_exp[a][1]) * factorial(g_exp[a][2]));
+            w += 0.5 * ma * L[a * N + i];
+            if (order_of(a) <= 2)
+                for (int k = 0; k < 3; ++k) f[k] -= ma * L[sum_index(a, ek[k]) * N + i];
+        }
+        for (int k = 0; k < 3; ++k) F[k * N + i] = f[k];
+        W[i] = w;
+    }
+    return 0;
+}
