@@ -77,6 +77,8 @@ def main():
                     help="sub-grids per axis of the batched-vs-per-sub-grid comparison (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time of the oracle baseline (0: skip)")
+    ap.add_argument("--tree-steps", type=int, default=10,
+                    help="timed launches of each tree pass (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counters)")
     args = ap.parse_args()
@@ -168,6 +170,11 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # ----------------------------------------- tree passes on the same store
+    tree = None
+    if args.tree_steps > 0 and args.n % 2 == 0:
+        tree = tree_passes(args.n, args.tree_steps, Md, Xd, L, ot, synthetic, np, torch, dev)
+
     # --------------------------------------- batched vs per-sub-grid launches
     per_sub = None
     if args.per_subgrid_n > 0:
@@ -211,10 +218,65 @@ def main():
         "fwd_bwd_frac_fp64_peak": round(fwdbwd_flops / PEAK_FP64_TFLOPS, 4),
         "fwd_pairs_per_s": fwd_pairs_s,
         "direct_launch_ms_per_step": round(sum_ms, 3),
+        "tree_passes": tree,
         "batched_vs_per_subgrid": per_sub,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# Algorithmic HBM bytes of the tree passes (FP64, every input read once and
+# every output written once):
+#   upward pass, per parent cell: 8 children x (20 moments + 3 centre) read,
+#     20 moments + 3 centre written                          -> 1656 B
+#   downward pass, per child cell: parent's 20 + 3 read once per 8 children,
+#     child centre (3) read, child coefficients (20) read and written -> 367 B
+#   evaluation, per cell: 20 moments + 20 coefficients read, 3 force
+#     components + 1 energy written                          -> 352 B
+TREE_BYTES = {"m2m": 1656, "l2l": 367, "evaluate": 352}
+PEAK_HBM_GBS = 8000.0
+
+
+def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev):
+    """Times the upward pass from the n^3 store to its (n/2)^3 parent level,
+    the downward pass back into the store's coefficients, and the local
+    evaluation over every cell; HIP events on the launch stream."""
+    ch = synthetic.octree_children(n)
+    Sp, S = ch.shape[0], n ** 3
+    tree = ot.Tree(ch, S)
+    f64 = dict(dtype=torch.float64, device=dev)
+    Mp = torch.empty((20, Sp * 512), **f64)
+    Xp = torch.empty((3, Sp * 512), **f64)
+    Lp = torch.randn((20, Sp * 512), generator=torch.Generator(device=dev).manual_seed(7), **f64)
+    F = torch.empty((3, S * 512), **f64)
+    W = torch.empty((S * 512,), **f64)
+    stream = torch.cuda.current_stream()
+    calls = {
+        "m2m": (lambda: tree.m2m(Md, Xd, Mp, Xp), Sp * 512),
+        "l2l": (lambda: tree.l2l(Lp, Xp, Xd, L), S * 512),
+        "evaluate": (lambda: ot.ot_fmm_evaluate(Md, L, F, W), S * 512),
+    }
+    out = {}
+    for name, (fn, units) in calls.items():
+        for _ in range(2):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = TREE_BYTES[name] * units / (ms * 1e-3) / 1e9
+        out[name] = {"mean_ms": round(ms, 4), "units": units, "unit": "parent cell" if name == "m2m"
+                     else "cell", "bytes_per_unit": TREE_BYTES[name],
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                  "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}}
+        log("tree %-9s %.3f ms  %.0f GB/s" % (name, ms, gbs))
+    tree.close()
+    return out
 
 
 def per_subgrid_comparison(n, ot, synthetic, np, torch, dev):

@@ -153,6 +153,50 @@ int ot_fmm_plan_timing(ot_fmm_plan plan, int enable);
 int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launches[3]);
 
 /* ---------------------------------------------------------------------------
+ * Tree passes around the interaction (paper Sec. 2.1 and 2.3: the FMM gravity
+ * solver traverses the octree of sub-grids). A parent node p has 8 child nodes
+ * children[p][o], o = ox + 2 oy + 4 oz (one octant each); parent cell
+ * (X, Y, Z) of p covers the 2x2x2 child cells (2(X%4)+a, 2(Y%4)+b, 2(Z%4)+c),
+ * a, b, c in {0, 1}, of child node o = (X/4) + 2(Y/4) + 4(Z/4). Parent and
+ * child stores use the batched layout ([ncomp][nodes*512]).
+ * ------------------------------------------------------------------------- */
+typedef struct ot_fmm_tree_s* ot_fmm_tree;
+
+/* children: HOST array [Sp][8] of child store ids in [0, Sc), each id at most
+ * once, 8*Sp <= 2^26 (EINVAL otherwise). Keeps a device copy; synchronous;
+ * bound to the current device (passes on another device return EINVAL).
+ * All device pointers of the passes: 16-byte aligned (EINVAL otherwise);
+ * the passes are asynchronous on `stream`, and outputs must not alias inputs. */
+int ot_fmm_tree_create(int32_t Sp, int32_t Sc, const int32_t* children, ot_fmm_tree* out);
+int ot_fmm_tree_destroy(ot_fmm_tree tree);
+
+/* Upward pass (M2M; P2M when the children carry only masses): for every
+ * parent cell, mass = sum of the 8 child masses, centre = their mass-weighted
+ * mean (plain mean if the mass is 0), raw moments about it
+ *   M_b(p) = sum_c sum_{g <= b} C(b, g) M_g(c) (X_c - X_p)^(b-g),
+ * exact to order 3. Mc[20][Sc*512], comc[3][Sc*512] -> Mp[20][Sp*512],
+ * comp[3][Sp*512] (overwritten). */
+int ot_fmm_m2m(ot_fmm_tree tree, const double* Mc, const double* comc, double* Mp, double* comp,
+               void* stream);
+
+/* Downward pass (L2L): every child cell's coefficients are INCREMENTED by its
+ * parent cell's local expansion re-expanded about the child centre,
+ *   L_a(c) += sum_{|g| <= 3-|a|} L_{a+g}(p) (X_c - X_p)^g / g!,
+ * exact for the cubic expansion. Lp[20][Sp*512], comp[3][Sp*512],
+ * comc[3][Sc*512], Lc[20][Sc*512] (in/out; cells of child nodes not listed
+ * in the tree are untouched). */
+int ot_fmm_l2l(ot_fmm_tree tree, const double* Lp, const double* comp, const double* comc,
+               double* Lc, void* stream);
+
+/* Local evaluation per cell, from its moments M (about its centre) and local
+ * coefficients L (about the same centre), with the expansion truncated at
+ * order 3:  F_k = - sum_{|a|<=2} M_a/a! L_{a+e_k}  (force on the cell's mass),
+ *           W   = 1/2 sum_{|a|<=3} M_a/a! L_a     (its share of the energy).
+ * M, L [20][ncells] -> F[3][ncells], W[ncells]; 1 <= ncells <= 2^38. */
+int ot_fmm_evaluate(int64_t ncells, const double* M, const double* L, double* F, double* W,
+                    void* stream);
+
+/* ---------------------------------------------------------------------------
  * Helpers
  * ------------------------------------------------------------------------- */
 const char* ot_fmm_strerror(int code);

@@ -215,7 +215,7 @@ def l2l(children, Lp, Xp, Xc, Lc, nthreads: int = 0):
     Lp = _f64(Lp)
     Xp = _f64(Xp)
     Xc = _f64(Xc)
-    out = np.array(Lc, dtype=np.float64, copy=True)
+    out = np.array(Lc, dtype=np.float64, order="C", copy=True)
     Sc = Xc.shape[1] // SUB3
     rc = _load().orc_l2l(ch.shape[0], Sc, _ptr(ch), _ptr(Lp), _ptr(Xp), _ptr(Xc), _ptr(out),
                          nthreads)

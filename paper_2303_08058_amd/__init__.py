@@ -72,6 +72,17 @@ _lib.ot_fmm_plan_timing.restype = _I
 _lib.ot_fmm_plan_kernel_times.argtypes = [_P, _P, _P]
 _lib.ot_fmm_plan_kernel_times.restype = _I
 
+_lib.ot_fmm_tree_create.argtypes = [_I32, _I32, _P, ctypes.POINTER(_P)]
+_lib.ot_fmm_tree_create.restype = _I
+_lib.ot_fmm_tree_destroy.argtypes = [_P]
+_lib.ot_fmm_tree_destroy.restype = _I
+_lib.ot_fmm_m2m.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.ot_fmm_m2m.restype = _I
+_lib.ot_fmm_l2l.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.ot_fmm_l2l.restype = _I
+_lib.ot_fmm_evaluate.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P]
+_lib.ot_fmm_evaluate.restype = _I
+
 KERNELS = ("forward", "adjoint_source", "adjoint_target")
 
 
@@ -276,3 +287,70 @@ class MultipoleBatched(torch.autograd.Function):
 def multipole(M, com, plan):
     """Differentiable batched multipole interaction (see MultipoleBatched)."""
     return MultipoleBatched.apply(M, com, plan)
+
+
+# ---------------------------------------------------------------------------
+# tree passes around the interaction
+# ---------------------------------------------------------------------------
+class Tree:
+    """Parent -> 8 children table of one octree level (ot_fmm_tree)."""
+
+    def __init__(self, children, Sc):
+        ch = np.ascontiguousarray(children, dtype=np.int32)
+        if ch.ndim != 2 or ch.shape[1] != 8:
+            raise ValueError("children must be (Sp, 8)")
+        self.Sp = int(ch.shape[0])
+        self.Sc = int(Sc)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(_lib.ot_fmm_tree_create(self.Sp, self.Sc, ch.ctypes.data_as(_P), ctypes.byref(h)),
+               "ot_fmm_tree_create")
+        self._h = h
+
+    def close(self):
+        if self._h is not None:
+            _lib.ot_fmm_tree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("tree is closed")
+        return self._h
+
+    def m2m(self, Mc, comc, Mp, comp, stream=None):
+        nc, npar = self.Sc * 512, self.Sp * 512
+        _check(_lib.ot_fmm_m2m(self.handle, _dptr(Mc, (20, nc), "Mc"), _dptr(comc, (3, nc), "comc"),
+                               _dptr(Mp, (20, npar), "Mp"), _dptr(comp, (3, npar), "comp"),
+                               _stream(stream)), "ot_fmm_m2m")
+        return Mp, comp
+
+    def l2l(self, Lp, comp, comc, Lc, stream=None):
+        nc, npar = self.Sc * 512, self.Sp * 512
+        _check(_lib.ot_fmm_l2l(self.handle, _dptr(Lp, (20, npar), "Lp"), _dptr(comp, (3, npar), "comp"),
+                               _dptr(comc, (3, nc), "comc"), _dptr(Lc, (20, nc), "Lc"),
+                               _stream(stream)), "ot_fmm_l2l")
+        return Lc
+
+
+def ot_fmm_m2m(tree, Mc, comc, Mp, comp, stream=None):
+    return tree.m2m(Mc, comc, Mp, comp, stream)
+
+
+def ot_fmm_l2l(tree, Lp, comp, comc, Lc, stream=None):
+    return tree.l2l(Lp, comp, comc, Lc, stream)
+
+
+def ot_fmm_evaluate(M, L, F, W, stream=None):
+    """M, L (20, n) -> F (3, n), W (n,) per-cell force and energy share."""
+    n = int(M.shape[1])
+    _check(_lib.ot_fmm_evaluate(n, _dptr(M, (20, n), "M"), _dptr(L, (20, n), "L"),
+                                _dptr(F, (3, n), "F"), _dptr(W, (n,), "W"), _stream(stream)),
+           "ot_fmm_evaluate")
+    return F, W

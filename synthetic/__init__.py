@@ -214,6 +214,28 @@ def lattice_batch(n, periodic=True):
     return batch
 
 
+def octree_children(n):
+    """Parent level of an n^3 store (n even): parent node P = px + m py + m^2 pz
+    (m = n/2) has child o = ox + 2 oy + 4 oz at store id
+    (2px+ox) + n (2py+oy) + n^2 (2pz+oz). Returns int32 (m^3, 8)."""
+    assert n % 2 == 0
+    m = n // 2
+    P = np.arange(m ** 3)
+    pc = np.stack([P % m, (P // m) % m, P // (m * m)], axis=1)
+    o = np.arange(8)
+    oc = np.stack([o & 1, (o >> 1) & 1, o >> 2], axis=1)
+    c = 2 * pc[:, None, :] + oc[None, :, :]
+    return (c[..., 0] + n * c[..., 1] + n * n * c[..., 2]).astype(np.int32)
+
+
+def local_field(ncell, rng, h=1.0):
+    """Synthetic local expansion coefficients L (20, ncell): N(0, 1) scaled by
+    h^-|a| (the size of a derivative of order |a| of a smooth potential)."""
+    L = rng.standard_normal((NM, ncell))
+    order = np.array([sum(e) for e in moment_exponents(3)])
+    return L * (h ** -order.astype(np.float64))[:, None]
+
+
 def apply_missing(batch, frac, rng):
     """Seeded missing-neighbour mask: round(frac*T) targets drawn uniformly,
     each losing k ~ U{1..9} distinct neighbours out of its 26."""

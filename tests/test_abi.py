@@ -113,3 +113,28 @@ def test_kernels_reject_null_and_misaligned_pointers(lib):
     assert lib.ot_fmm_multipole_batched(None, None, None, None, 0, None) == -1
     lib.ot_fmm_last_error.restype = ctypes.c_char_p
     assert lib.ot_fmm_last_error() != b""
+
+
+@pytest.mark.parametrize("case", ["range", "twice", "zero"])
+def test_tree_create_rejects_bad_tables(lib, case):
+    P = ctypes.c_void_p
+    lib.ot_fmm_tree_create.argtypes = [ctypes.c_int32, ctypes.c_int32, P, ctypes.POINTER(P)]
+    ch = np.arange(16, dtype=np.int32).reshape(2, 8)
+    Sp, Sc = 2, 16
+    if case == "range":
+        ch[1, 3] = 16
+    elif case == "twice":
+        ch[1, 3] = 2
+    else:
+        Sp = 0
+    h = P()
+    assert lib.ot_fmm_tree_create(Sp, Sc, ch.ctypes.data_as(P), ctypes.byref(h)) == -1
+
+
+def test_evaluate_rejects_bad_sizes(lib):
+    P = ctypes.c_void_p
+    lib.ot_fmm_evaluate.argtypes = [ctypes.c_int64, P, P, P, P, P]
+    buf = (ctypes.c_double * 64)()
+    base = ctypes.addressof(buf)
+    assert lib.ot_fmm_evaluate(0, base, base, base, base, None) == -1
+    assert lib.ot_fmm_evaluate(4, None, base, base, base, None) == -1

@@ -256,3 +256,22 @@ def test_evaluate_pair_newton_and_energy_symmetry():
     F, W = oracle.evaluate(M[:, [ii, jj]], L[:, [ti, tj]])
     assert np.all(np.abs(F[:, 0] + F[:, 1]) <= 1e-14 * np.abs(F).max())
     assert abs(W[0] - W[1]) <= 1e-14 * abs(W[0])
+
+
+def test_wrappers_accept_non_contiguous_inputs():
+    """Column-gathered (Fortran-ordered) arrays give the same results as their
+    C-ordered copies."""
+    rng = np.random.default_rng(14)
+    ch = random_children(1, rng)
+    cols = rng.permutation(8 * SUB3)
+    Lc = rng.standard_normal((20, 8 * SUB3))[:, cols]
+    Xc = rng.uniform(0, 8, (3, 8 * SUB3))[:, cols]
+    Lp = rng.standard_normal((20, SUB3))
+    Xp = rng.uniform(0, 8, (3, SUB3))
+    assert not Lc.flags["C_CONTIGUOUS"]
+    a = oracle.l2l(ch, Lp, Xp, Xc, Lc)
+    b = oracle.l2l(ch, Lp, Xp, np.ascontiguousarray(Xc), np.ascontiguousarray(Lc))
+    assert np.array_equal(a, b)
+    F1, W1 = oracle.evaluate(Lc, Lc)
+    F2, W2 = oracle.evaluate(np.ascontiguousarray(Lc), np.ascontiguousarray(Lc))
+    assert np.array_equal(F1, F2) and np.array_equal(W1, W2)
