@@ -44,6 +44,10 @@ FLOP_PER_PAIR = {
 }
 
 
+# sources of the interaction kernels (the counter record names their hash)
+INTERACTION_SOURCES = ("ot_common.h", "ot_fmm.hip")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -54,11 +58,13 @@ def measured_traffic(kernel, sched, n):
     on this kernel source and this workload; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_32768_subgrids.json")
-    src = os.path.join(ROOT, "paper_2303_08058_amd", "csrc", "ot_fmm.hip")
     if n != 32 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec.get("source_sha256_16"):
+    h = hashlib.sha256()
+    for f in INTERACTION_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2303_08058_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
     key = {"forward": "forward", "adjoint_source": "adjoint_source",
            "adjoint_target": "adjoint_target"}[kernel]
@@ -276,6 +282,24 @@ def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev):
                                   "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}}
         log("tree %-9s %.3f ms  %.0f GB/s" % (name, ms, gbs))
     tree.close()
+    # a plain device copy of 2 GiB on the same stream, as the attainable
+    # read+write bandwidth these streaming kernels compare with
+    a = torch.empty(1 << 28, **f64)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out["copy_2GiB"] = {"mean_ms": round(ms, 4),
+                        "gbs": round(2 * a.numel() * 8 / (ms * 1e-3) / 1e9, 1)}
+    log("copy 2 GiB      %.3f ms  %.0f GB/s" % (ms, out["copy_2GiB"]["gbs"]))
+    del a, b
     return out
 
 

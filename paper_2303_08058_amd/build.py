@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ot_fmm.hip")
+SRC = [os.path.join(HERE, "csrc", "ot_fmm.hip"), os.path.join(HERE, "csrc", "ot_tree.hip")]
 HDR = os.path.join(ROOT, "include", "ot_fmm.h")
 LIB = os.path.join(HERE, "libotfmm.so")
 
@@ -29,9 +29,9 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile csrc/ot_fmm.hip into libotfmm.so (always recompiles)."""
+    """Compile csrc/*.hip into libotfmm.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + SRC
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -47,100 +47,12 @@
 #include <utility>
 #include <vector>
 
+#include "ot_common.h"
 #include "ot_fmm.h"
 
+using namespace otfmm;
+
 namespace {
-
-// ---------------------------------------------------------------------------
-// Errors
-// ---------------------------------------------------------------------------
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg)
-{
-    g_last_error = msg;
-    return code;
-}
-
-int hip_fail(hipError_t e, const char* what)
-{
-    return fail(OT_FMM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-#define OT_HIP(call)                                   \
-    do {                                               \
-        hipError_t e_ = (call);                        \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// Geometry constants
-// ---------------------------------------------------------------------------
-constexpr int kSub = 8;
-constexpr int kSub3 = 512;
-constexpr int kHalo = 24;
-constexpr int kPlane = kHalo * kHalo;   // 576 cells per halo z-plane
-constexpr int kHalo3 = kPlane * kHalo;  // 13824
-constexpr int kReach = 9;               // max |d_k| in the stencil
-constexpr int kMaxRows = 2 * (2 * kReach + 1) * (2 * kReach + 1);
-constexpr double kFar = 1.0e20;         // centre used for missing cells
-
-// ---------------------------------------------------------------------------
-// Multi-indices, graded lexicographic with x most significant
-// ---------------------------------------------------------------------------
-struct Exp3 {
-    int a, b, c;
-};
-
-__host__ __device__ constexpr int ncomp(int o) { return (o + 1) * (o + 2) * (o + 3) / 6; }
-
-__host__ __device__ constexpr Exp3 exp_of(int g)
-{
-    int k = 0;
-    for (int n = 0; n <= 8; ++n)
-        for (int a = n; a >= 0; --a)
-            for (int b = n - a; b >= 0; --b) {
-                if (k == g) return Exp3{a, b, n - a - b};
-                ++k;
-            }
-    return Exp3{-1, -1, -1};
-}
-
-__host__ __device__ constexpr int ord_of(int g)
-{
-    return exp_of(g).a + exp_of(g).b + exp_of(g).c;
-}
-
-__host__ __device__ constexpr int idx_of(int a, int b, int c)
-{
-    const int n = a + b + c;
-    int k = n > 0 ? ncomp(n - 1) : 0;
-    for (int ap = n; ap > a; --ap) k += n - ap + 1;
-    return k + (n - a) - b;
-}
-
-__host__ __device__ constexpr int sum_idx(int g, int h)
-{
-    return idx_of(exp_of(g).a + exp_of(h).a, exp_of(g).b + exp_of(h).b,
-                  exp_of(g).c + exp_of(h).c);
-}
-
-__host__ __device__ constexpr double factorial(int n) { return n <= 1 ? 1.0 : n * factorial(n - 1); }
-
-__host__ __device__ constexpr double inv_multi_factorial(int g)
-{
-    return 1.0 / (factorial(exp_of(g).a) * factorial(exp_of(g).b) * factorial(exp_of(g).c));
-}
-
-__host__ __device__ constexpr double parity_sign(int g) { return (ord_of(g) & 1) ? -1.0 : 1.0; }
-
-constexpr bool check_indices()
-{
-    for (int g = 0; g < 35; ++g)
-        if (idx_of(exp_of(g).a, exp_of(g).b, exp_of(g).c) != g) return false;
-    return ord_of(19) == 3 && ord_of(20) == 4 && sum_idx(1, 2) == 5 && sum_idx(4, 3) == 12;
-}
-static_assert(check_indices(), "multi-index tables");
 
 // Staging scale of the source components: forward sources carry
 // s_beta = (-1)^{|beta|}/beta!, adjoint sources carry (-1)^{|alpha|}.
@@ -912,232 +824,19 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     }
 }
 
-// ---------------------------------------------------------------------------
-// Tree passes around the interaction (paper Sec. 2.1 / 2.3: the FMM gravity
-// solver works on the octree of sub-grids). A parent node p has 8 child nodes
-// children[p][o], o = ox + 2 oy + 4 oz; parent cell (X, Y, Z) covers the 2x2x2
-// child cells (2 (X % 4) + a, 2 (Y % 4) + b, 2 (Z % 4) + c) of child o =
-// (X / 4, Y / 4, Z / 4). These kernels are bound by HBM bandwidth.
-// ---------------------------------------------------------------------------
-template <int B, int G>
-__device__ __forceinline__ void shift_term(double* acc, const double* m, const double* mono)
-{
-    // acc_B += C(B, G) m_G d^(B - G) for G <= B componentwise
-    constexpr Exp3 b = exp_of(B), g = exp_of(G);
-    if constexpr (g.a <= b.a && g.b <= b.b && g.c <= b.c) {
-        constexpr double c = factorial(b.a) / (factorial(g.a) * factorial(b.a - g.a)) *
-                             factorial(b.b) / (factorial(g.b) * factorial(b.b - g.b)) *
-                             factorial(b.c) / (factorial(g.c) * factorial(b.c - g.c));
-        constexpr int e = idx_of(b.a - g.a, b.b - g.b, b.c - g.c);
-        if constexpr (c == 1.0)
-            acc[B] = __builtin_fma(m[G], mono[e], acc[B]);
-        else
-            acc[B] = __builtin_fma(c * m[G], mono[e], acc[B]);
-    }
-}
-template <int B, int... G>
-__device__ __forceinline__ void shift_row(double* acc, const double* m, const double* mono,
-                                          std::integer_sequence<int, G...>)
-{
-    (shift_term<B, G>(acc, m, mono), ...);
-}
-template <int... B>
-__device__ __forceinline__ void moment_shift(double* acc, const double* m, const double* mono,
-                                             std::integer_sequence<int, B...>)
-{
-    (shift_row<B>(acc, m, mono, std::make_integer_sequence<int, 20>{}), ...);
-}
-
-// the 20 monomials d^e, |e| <= 3, graded-lex order
-__device__ __forceinline__ void monomials(double x, double y, double z, double* t)
-{
-    t[0] = 1.0;
-    t[1] = x;
-    t[2] = y;
-    t[3] = z;
-    t[4] = x * x;
-    t[5] = x * y;
-    t[6] = x * z;
-    t[7] = y * y;
-    t[8] = y * z;
-    t[9] = z * z;
-    t[10] = t[4] * x;
-    t[11] = t[4] * y;
-    t[12] = t[4] * z;
-    t[13] = x * t[7];
-    t[14] = t[5] * z;
-    t[15] = x * t[9];
-    t[16] = t[7] * y;
-    t[17] = t[7] * z;
-    t[18] = y * t[9];
-    t[19] = t[9] * z;
-}
-
-struct TreeParams {
-    const int* children;  // [Sp][8]
-    const double* m_in;   // M2M: child moments; L2L: parent coefficients
-    const double* x_in;   // M2M: child centres; L2L: parent centres
-    const double* x_in2;  // L2L: child centres
-    double* m_out;        // M2M: parent moments; L2L: child coefficients (accumulated)
-    double* x_out;        // M2M: parent centres
-    long n_child, n_parent;  // cells per component in child / parent stores
-    int Sp;
-};
-
-// Upward pass: one thread per parent cell.
-__global__ void __launch_bounds__(256) k_m2m(const TreeParams p)
-{
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)p.Sp * kSub3) return;
-    const int node = (int)(t >> 9), pc = (int)(t & 511);
-    const int X = pc & 7, Y = (pc >> 3) & 7, Z = pc >> 6;
-    const int o = (X >> 2) + 2 * (Y >> 2) + 4 * (Z >> 2);
-    const long base = (long)p.children[node * 8 + o] * kSub3;
-    const int l0 = 2 * (X & 3) + 8 * 2 * (Y & 3) + 64 * 2 * (Z & 3);
-    double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const long j = base + l0 + (k & 1) + 8 * ((k >> 1) & 1) + 64 * (k >> 2);
-        const double mk = p.m_in[j];
-        const double xk = p.x_in[j], yk = p.x_in[p.n_child + j], zk = p.x_in[2 * p.n_child + j];
-        m += mk;
-        mx = __builtin_fma(mk, xk, mx);
-        my = __builtin_fma(mk, yk, my);
-        mz = __builtin_fma(mk, zk, mz);
-        gx += xk;
-        gy += yk;
-        gz += zk;
-    }
-    double cx, cy, cz;
-    if (m > 0.0) {
-        cx = mx / m;
-        cy = my / m;
-        cz = mz / m;
-    } else {
-        cx = gx * 0.125;
-        cy = gy * 0.125;
-        cz = gz * 0.125;
-    }
-    double acc[20];
-#pragma unroll
-    for (int b = 0; b < 20; ++b) acc[b] = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        const long j = base + l0 + (k & 1) + 8 * ((k >> 1) & 1) + 64 * (k >> 2);
-        double mm[20], mono[20];
-#pragma unroll
-        for (int b = 0; b < 20; ++b) mm[b] = p.m_in[b * p.n_child + j];
-        monomials(p.x_in[j] - cx, p.x_in[p.n_child + j] - cy, p.x_in[2 * p.n_child + j] - cz, mono);
-        moment_shift(acc, mm, mono, std::make_integer_sequence<int, 20>{});
-    }
-    const long q = (long)node * kSub3 + pc;
-#pragma unroll
-    for (int b = 0; b < 20; ++b) p.m_out[b * p.n_parent + q] = acc[b];
-    p.x_out[q] = cx;
-    p.x_out[p.n_parent + q] = cy;
-    p.x_out[2 * p.n_parent + q] = cz;
-}
-
-// L_A(child) += sum_{|G| <= 3 - |A|} L_{A+G}(parent) d^G / G!
-template <int A, int G>
-__device__ __forceinline__ void l2l_term(double& acc, const double* lp, const double* mono)
-{
-    if constexpr (ord_of(A) + ord_of(G) <= 3) {
-        constexpr int S = sum_idx(A, G);
-        constexpr double f = inv_multi_factorial(G);
-        if constexpr (f == 1.0)
-            acc = __builtin_fma(lp[S], mono[G], acc);
-        else
-            acc = __builtin_fma(lp[S] * f, mono[G], acc);
-    }
-}
-template <int A, int... G>
-__device__ __forceinline__ void l2l_row(double* out, const double* lp, const double* mono,
-                                        std::integer_sequence<int, G...>)
-{
-    double acc = 0.0;
-    (l2l_term<A, G>(acc, lp, mono), ...);
-    out[A] += acc;
-}
-template <int... A>
-__device__ __forceinline__ void l2l_shift(double* out, const double* lp, const double* mono,
-                                          std::integer_sequence<int, A...>)
-{
-    (l2l_row<A>(out, lp, mono, std::make_integer_sequence<int, 20>{}), ...);
-}
-
-// Downward pass: one thread per child cell (the child node of parent `node`
-// at octant o, cell c); each child node has one parent, so writes never race.
-__global__ void __launch_bounds__(256) k_l2l(const TreeParams p)
-{
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long)p.Sp * 8 * kSub3) return;
-    const int node = (int)(t >> 12), o = (int)((t >> 9) & 7), c = (int)(t & 511);
-    const int x = c & 7, y = (c >> 3) & 7, z = c >> 6;
-    const int pc = (x >> 1) + 4 * (o & 1) + 8 * ((y >> 1) + 4 * ((o >> 1) & 1)) +
-                   64 * ((z >> 1) + 4 * (o >> 2));
-    const long ip = (long)node * kSub3 + pc;
-    const long j = (long)p.children[node * 8 + o] * kSub3 + c;
-    double lp[20], mono[20], out[20];
-#pragma unroll
-    for (int a = 0; a < 20; ++a) lp[a] = p.m_in[a * p.n_parent + ip];
-#pragma unroll
-    for (int a = 0; a < 20; ++a) out[a] = p.m_out[a * p.n_child + j];
-    monomials(p.x_in2[j] - p.x_in[ip], p.x_in2[p.n_child + j] - p.x_in[p.n_parent + ip],
-              p.x_in2[2 * p.n_child + j] - p.x_in[2 * p.n_parent + ip], mono);
-    l2l_shift(out, lp, mono, std::make_integer_sequence<int, 20>{});
-#pragma unroll
-    for (int a = 0; a < 20; ++a) p.m_out[a * p.n_child + j] = out[a];
-}
-
-// F_k = - sum_{|a| <= 2} M_a / a! L_{a+e_k},  W = 1/2 sum_{|a| <= 3} M_a / a! L_a
-template <int A>
-__device__ __forceinline__ void eval_term(const double* m, const double* l, double* f, double& w)
-{
-    constexpr double inv = inv_multi_factorial(A);
-    const double ma = (inv == 1.0) ? m[A] : m[A] * inv;
-    w = __builtin_fma(ma, l[A], w);
-    if constexpr (ord_of(A) <= 2) {
-        f[0] = __builtin_fma(-ma, l[sum_idx(A, 1)], f[0]);
-        f[1] = __builtin_fma(-ma, l[sum_idx(A, 2)], f[1]);
-        f[2] = __builtin_fma(-ma, l[sum_idx(A, 3)], f[2]);
-    }
-}
-template <int... A>
-__device__ __forceinline__ void eval_all(const double* m, const double* l, double* f, double& w,
-                                         std::integer_sequence<int, A...>)
-{
-    (eval_term<A>(m, l, f, w), ...);
-}
-
-__global__ void __launch_bounds__(256) k_evaluate(const double* M, const double* L, double* F,
-                                                  double* W, long n)
-{
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double m[20], l[20], f[3] = {0.0, 0.0, 0.0}, w = 0.0;
-#pragma unroll
-    for (int a = 0; a < 20; ++a) {
-        m[a] = M[a * n + i];
-        l[a] = L[a * n + i];
-    }
-    eval_all(m, l, f, w, std::make_integer_sequence<int, 20>{});
-    F[i] = f[0];
-    F[n + i] = f[1];
-    F[2 * n + i] = f[2];
-    W[i] = 0.5 * w;
-}
-
 }  // namespace
 
 // ===========================================================================
 // Host side
 // ===========================================================================
-namespace {
+namespace otfmm {
 
+namespace {
 constexpr int kMaxDevices = 64;
 std::mutex g_dev_mutex;
 int g_dev_state[kMaxDevices];  // 0 unknown, 1 gfx950 ready, -1 unsupported
+
+}  // namespace
 
 int ensure_device()
 {
@@ -1161,7 +860,10 @@ int ensure_device()
     return OT_FMM_OK;
 }
 
-bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+}  // namespace otfmm
+
+namespace {
+
 
 template <int MODE, int NW, bool SPLIT = false>
 int launch(const KParams& kp, int nblocks, hipStream_t stream)
@@ -1180,12 +882,6 @@ int pick_fwd(int sched, int tuned)
 }
 
 }  // namespace
-
-struct ot_fmm_tree_s {
-    int device = 0;
-    int32_t Sp = 0, Sc = 0;
-    int* d_children = nullptr;  // [Sp][8]
-};
 
 struct ot_fmm_plan_s {
     int device = 0;
@@ -1339,21 +1035,6 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_tgt);
     (void)hipFree(p->d_fwd_order);
     (void)hipFree(p->d_rev_order);
-}
-
-template <class Tp>
-int upload(Tp** dst, const std::vector<Tp>& src)
-{
-    *dst = nullptr;
-    if (src.empty()) return OT_FMM_OK;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(Tp));
-    if (e != hipSuccess) {
-        *dst = nullptr;
-        return fail(OT_FMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    e = hipMemcpy(*dst, src.data(), src.size() * sizeof(Tp), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-    return OT_FMM_OK;
 }
 
 // Work order: longest work first (a greedy longest-processing-time list for
@@ -1694,122 +1375,6 @@ int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launc
         plan->ev_used[w] = 0;
     }
     return OT_FMM_OK;
-}
-
-int ot_fmm_tree_create(int32_t Sp, int32_t Sc, const int32_t* children, ot_fmm_tree* out)
-{
-    g_last_error.clear();
-    if (!out) return fail(OT_FMM_EINVAL, "null output pointer");
-    *out = nullptr;
-    if (Sp <= 0 || Sc <= 0 || !children) return fail(OT_FMM_EINVAL, "Sp, Sc > 0 and children required");
-    // keeps every launch grid (one thread per child cell) below 2^27 work-groups
-    if ((int64_t)Sp * 8 > ((int64_t)1 << 26)) return fail(OT_FMM_EINVAL, "tree too large");
-    std::vector<char> used(Sc, 0);
-    for (int64_t i = 0; i < (int64_t)Sp * 8; ++i) {
-        const int32_t c = children[i];
-        if (c < 0 || c >= Sc) return fail(OT_FMM_EINVAL, "child id out of range");
-        if (used[c]) return fail(OT_FMM_EINVAL, "a child node appears under two parents");
-        used[c] = 1;
-    }
-    int rc = ensure_device();
-    if (rc) return rc;
-    ot_fmm_tree t = new (std::nothrow) ot_fmm_tree_s();
-    if (!t) return fail(OT_FMM_ENOMEM, "host allocation failed");
-    hipError_t e = hipGetDevice(&t->device);
-    if (e != hipSuccess) {
-        delete t;
-        return hip_fail(e, "hipGetDevice");
-    }
-    t->Sp = Sp;
-    t->Sc = Sc;
-    std::vector<int> ch(children, children + (int64_t)Sp * 8);
-    if ((rc = upload(&t->d_children, ch))) {
-        (void)hipFree(t->d_children);
-        delete t;
-        return rc;
-    }
-    *out = t;
-    return OT_FMM_OK;
-}
-
-int ot_fmm_tree_destroy(ot_fmm_tree tree)
-{
-    g_last_error.clear();
-    if (!tree) return OT_FMM_OK;
-    (void)hipFree(tree->d_children);
-    delete tree;
-    return OT_FMM_OK;
-}
-
-static int check_tree(ot_fmm_tree tree)
-{
-    if (!tree) return fail(OT_FMM_EINVAL, "null tree");
-    int dev = -1;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev != tree->device) return fail(OT_FMM_EINVAL, "tree belongs to another device");
-    return OT_FMM_OK;
-}
-
-int ot_fmm_m2m(ot_fmm_tree tree, const double* Mc, const double* comc, double* Mp, double* comp,
-               void* stream)
-{
-    g_last_error.clear();
-    int rc = check_tree(tree);
-    if (rc) return rc;
-    if (!aligned16(Mc) || !aligned16(comc) || !aligned16(Mp) || !aligned16(comp))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
-    TreeParams tp{};
-    tp.children = tree->d_children;
-    tp.m_in = Mc;
-    tp.x_in = comc;
-    tp.m_out = Mp;
-    tp.x_out = comp;
-    tp.n_child = (long)tree->Sc * kSub3;
-    tp.n_parent = (long)tree->Sp * kSub3;
-    tp.Sp = tree->Sp;
-    const long n = (long)tree->Sp * kSub3;
-    hipLaunchKernelGGL(k_m2m, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, tp);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
-}
-
-int ot_fmm_l2l(ot_fmm_tree tree, const double* Lp, const double* comp, const double* comc,
-               double* Lc, void* stream)
-{
-    g_last_error.clear();
-    int rc = check_tree(tree);
-    if (rc) return rc;
-    if (!aligned16(Lp) || !aligned16(comp) || !aligned16(comc) || !aligned16(Lc))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
-    TreeParams tp{};
-    tp.children = tree->d_children;
-    tp.m_in = Lp;
-    tp.x_in = comp;
-    tp.x_in2 = comc;
-    tp.m_out = Lc;
-    tp.n_child = (long)tree->Sc * kSub3;
-    tp.n_parent = (long)tree->Sp * kSub3;
-    tp.Sp = tree->Sp;
-    const long n = (long)tree->Sp * 8 * kSub3;
-    hipLaunchKernelGGL(k_l2l, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, tp);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
-}
-
-int ot_fmm_evaluate(int64_t ncells, const double* M, const double* L, double* F, double* W,
-                    void* stream)
-{
-    g_last_error.clear();
-    if (ncells <= 0 || ncells > ((int64_t)1 << 38)) return fail(OT_FMM_EINVAL, "ncells out of range");
-    if (!aligned16(M) || !aligned16(L) || !aligned16(F) || !aligned16(W))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
-    int rc = ensure_device();
-    if (rc) return rc;
-    hipLaunchKernelGGL(k_evaluate, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0,
-                       (hipStream_t)stream, M, L, F, W, (long)ncells);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
 }
 
 }  // extern "C"

@@ -80,8 +80,15 @@ def child_cells(children, psel):
 
 
 def m2m_magnitudes(Mc, Xc, cells, Xp):
-    """A_b = sum over the 8 children k, sum over g <= b of C(b, g) |M_g(k)| |d_k^(b-g)|."""
+    """A_b = sum over the 8 children k, sum over g <= b of C(b, g) |M_g(k)| |d_k^e|
+    (e = b - g, d_k = X_k - X_p), plus the first-order terms of the same sum in
+    the rounding of d_k = X_k - X_p: C(b, g) |M_g(k)| e_i |d_k^(e - e_i)|
+    (|X_k,i| + |X_p,i|). The second part is the size of the centre-of-mass
+    rounding carried into the moments: a one-ulp difference in X_p (a fused
+    multiply-add in the mass-weighted sum on one side, not on the other) moves
+    a dipole that cancels to rounding level by |M_0| ulp(|X_p|)."""
     d = Xc[:, cells] - Xp[:, :, None]
+    xs = np.abs(Xc[:, cells]) + np.abs(Xp[:, :, None])
     aM = np.abs(Mc[:, cells])
     A = np.zeros((20, cells.shape[0]))
     for b, eb in enumerate(EXP):
@@ -89,7 +96,12 @@ def m2m_magnitudes(Mc, Xc, cells, Xp):
             e = tuple(eb[i] - eg[i] for i in range(3))
             if min(e) < 0:
                 continue
-            A[b] += (_binom(eb, eg) * aM[g] * _absmono(d, e)).sum(axis=1)
+            c = _binom(eb, eg) * aM[g]
+            A[b] += (c * _absmono(d, e)).sum(axis=1)
+            for i in range(3):
+                if e[i] > 0:
+                    ei = tuple(e[k] - (k == i) for k in range(3))
+                    A[b] += (c * e[i] * _absmono(d, ei) * xs[i]).sum(axis=1)
     return A
 
 
