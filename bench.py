@@ -373,6 +373,26 @@ def per_subgrid_comparison(n, ot, synthetic, np, torch, dev):
         res["speedup_vs_%dstream" % nstreams] = round(ms / batched_ms, 2)
         log("per-sub-grid launches on %2d stream(s): %.1f ms (%.1fx slower)"
             % (nstreams, ms, ms / batched_ms))
+    # the same launches as futures completed by event polling (32 pool
+    # streams, 4 worker threads polling between tasks), waited for by polling
+    Lf = torch.empty_like(Lh)
+    ex = ot.Executor(nstreams=32, nworkers=4)
+    for s in range(32):
+        ex.stream(s)  # create the pool streams outside the timed region
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    futs = [ex.multipole_async(Mh[t], Xh[t], Lf[t]) for t in range(T)]
+    for f in futs:
+        f.wait(120.0)
+    ms = (time.perf_counter() - t0) * 1e3
+    del futs
+    ex.close()
+    res["per_subgrid_futures_32stream_ms"] = round(ms, 2)
+    res["speedup_vs_futures_32stream"] = round(ms / batched_ms, 2)
+    res["futures_bitwise_equal_to_stream_launches"] = bool(torch.equal(Lf, Lh))
+    log("per-sub-grid launches as polled futures (32 streams): %.1f ms (%.1fx slower)"
+        % (ms, ms / batched_ms))
+    del Lf
     # same numbers as the batched launch up to summation order (the missing
     # cells add exact zeros): per target and output order, max |diff| / max |L|
     Lb = L.reshape(20, T, 512).permute(1, 0, 2)

@@ -52,7 +52,8 @@ enum {
     OT_FMM_EINVAL = -1,       /* invalid argument; nothing enqueued */
     OT_FMM_EHIP = -2,         /* HIP runtime or launch error */
     OT_FMM_ENOMEM = -3,       /* device allocation failed (plan creation only) */
-    OT_FMM_EUNSUPPORTED = -4  /* current device is not gfx950 / no device */
+    OT_FMM_EUNSUPPORTED = -4, /* current device is not gfx950 / no device */
+    OT_FMM_ETIMEDOUT = -5     /* ot_fmm_future_wait: not ready within the limit */
 };
 
 /* Schedules (how a target sub-grid's 512 cells are spread over wavefronts).
@@ -195,6 +196,69 @@ int ot_fmm_l2l(ot_fmm_tree tree, const double* Lp, const double* comp, const dou
  * M, L [20][ncells] -> F[3][ncells], W[ncells]; 1 <= ncells <= 2^38. */
 int ot_fmm_evaluate(int64_t ncells, const double* M, const double* L, double* F, double* W,
                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Futures for asynchronous per-sub-grid launches, completed by event polling
+ * (paper Sec. 3: the task scheduler polls GPU events between tasks and makes
+ * the futures of completed events ready, which runs their continuations; one
+ * thread polls at a time and the others skip; events not yet complete are
+ * kept for the next poll; nothing ever blocks on the GPU).
+ *
+ * An executor owns `nstreams` HIP streams (created on first use, on the
+ * device current then; default priority) and a task queue served by
+ * `nworkers` threads (0: tasks run in the threads that call poll or wait).
+ * Workers run tasks and poll between them while events are pending. All
+ * calls are thread-safe. Futures must be released before their executor is
+ * destroyed; ot_fmm_executor_destroy first waits (by polling) for every
+ * registered event and runs the remaining tasks.
+ * ------------------------------------------------------------------------- */
+typedef struct ot_fmm_executor_s* ot_fmm_executor;
+typedef struct ot_fmm_future_s* ot_fmm_future;
+typedef void (*ot_fmm_callback)(void* user);
+
+/* 1 <= nstreams <= 1024, 0 <= nworkers <= 256 (EINVAL otherwise). Makes no
+ * HIP call. */
+int ot_fmm_executor_create(int nstreams, int nworkers, ot_fmm_executor* out);
+int ot_fmm_executor_destroy(ot_fmm_executor ex);
+
+/* Stream i (0 <= i < nstreams) of the pool, as a hipStream_t. */
+int ot_fmm_executor_stream(ot_fmm_executor ex, int i, void** stream);
+
+/* A new future that becomes ready when all work enqueued on `stream` before
+ * this call has completed (an event recorded on it). The caller owns one
+ * reference (ot_fmm_future_release). */
+int ot_fmm_executor_get_future(ot_fmm_executor ex, void* stream, ot_fmm_future* out);
+
+/* ot_fmm_multipole (single 24^3 halo block, same arguments and layout) on the
+ * next stream of the pool (round robin), plus its future. */
+int ot_fmm_executor_multipole_async(ot_fmm_executor ex, const double* M, const double* com,
+                                    double* L, ot_fmm_future* out);
+
+/* Queues fn(user) on the executor's task queue. */
+int ot_fmm_executor_post(ot_fmm_executor ex, ot_fmm_callback fn, void* user);
+
+/* One poll: *completed = futures made ready, or -1 if another thread was
+ * polling (the call then returns at once). Without workers it also runs the
+ * queued tasks. `completed` may be NULL. */
+int ot_fmm_executor_poll(ot_fmm_executor ex, int* completed);
+
+/* Number of registered events not yet seen complete. */
+int ot_fmm_executor_outstanding(ot_fmm_executor ex, int64_t* n);
+
+/* A host-side future, made ready by ot_fmm_future_set_ready (once; EINVAL
+ * for a second call or for an event-backed future). */
+int ot_fmm_future_create(ot_fmm_executor ex, ot_fmm_future* out);
+int ot_fmm_future_set_ready(ot_fmm_future f);
+
+/* Runs fn(user) as a task once f is ready (queued at once if it already is). */
+int ot_fmm_future_then(ot_fmm_future f, ot_fmm_callback fn, void* user);
+int ot_fmm_future_is_ready(ot_fmm_future f, int* ready);
+
+/* Waits until f is ready by running queued tasks and polling (never a
+ * blocking GPU call). timeout_s < 0: no limit; otherwise ETIMEDOUT after
+ * that many seconds. EHIP if the GPU work behind the future failed. */
+int ot_fmm_future_wait(ot_fmm_future f, double timeout_s);
+int ot_fmm_future_release(ot_fmm_future f);
 
 /* ---------------------------------------------------------------------------
  * Helpers

@@ -14,7 +14,9 @@ lexicographic order).
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
+import threading
 
 import numpy as np
 import torch
@@ -27,6 +29,7 @@ OT_FMM_EINVAL = -1
 OT_FMM_EHIP = -2
 OT_FMM_ENOMEM = -3
 OT_FMM_EUNSUPPORTED = -4
+OT_FMM_ETIMEDOUT = -5
 
 SCHED_AUTO = 0
 SCHED_W8 = 1
@@ -82,6 +85,27 @@ _lib.ot_fmm_l2l.argtypes = [_P, _P, _P, _P, _P, _P]
 _lib.ot_fmm_l2l.restype = _I
 _lib.ot_fmm_evaluate.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P]
 _lib.ot_fmm_evaluate.restype = _I
+
+_CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p)
+_lib.ot_fmm_executor_create.argtypes = [_I, _I, ctypes.POINTER(_P)]
+_lib.ot_fmm_executor_destroy.argtypes = [_P]
+_lib.ot_fmm_executor_stream.argtypes = [_P, _I, ctypes.POINTER(_P)]
+_lib.ot_fmm_executor_get_future.argtypes = [_P, _P, ctypes.POINTER(_P)]
+_lib.ot_fmm_executor_multipole_async.argtypes = [_P, _P, _P, _P, ctypes.POINTER(_P)]
+_lib.ot_fmm_executor_post.argtypes = [_P, _CB, _P]
+_lib.ot_fmm_executor_poll.argtypes = [_P, ctypes.POINTER(_I)]
+_lib.ot_fmm_executor_outstanding.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
+_lib.ot_fmm_future_create.argtypes = [_P, ctypes.POINTER(_P)]
+_lib.ot_fmm_future_set_ready.argtypes = [_P]
+_lib.ot_fmm_future_then.argtypes = [_P, _CB, _P]
+_lib.ot_fmm_future_is_ready.argtypes = [_P, ctypes.POINTER(_I)]
+_lib.ot_fmm_future_wait.argtypes = [_P, ctypes.c_double]
+_lib.ot_fmm_future_release.argtypes = [_P]
+for _n in ("executor_create", "executor_destroy", "executor_stream", "executor_get_future",
+           "executor_multipole_async", "executor_post", "executor_poll", "executor_outstanding",
+           "future_create", "future_set_ready", "future_then", "future_is_ready", "future_wait",
+           "future_release"):
+    getattr(_lib, "ot_fmm_" + _n).restype = _I
 
 KERNELS = ("forward", "adjoint_source", "adjoint_target")
 
@@ -354,3 +378,119 @@ def ot_fmm_evaluate(M, L, F, W, stream=None):
                                 _dptr(F, (3, n), "F"), _dptr(W, (n,), "W"), _stream(stream)),
            "ot_fmm_evaluate")
     return F, W
+
+
+# ---------------------------------------------------------------------------
+# futures completed by event polling
+# ---------------------------------------------------------------------------
+_callables = {}
+_callables_lock = threading.Lock()
+_next_key = itertools.count(1)
+
+
+def _dispatch(user):
+    with _callables_lock:
+        fn = _callables.pop(user)
+    fn()
+
+
+_DISPATCH = _CB(_dispatch)  # one C entry for every Python callable (kept alive)
+
+
+def _register(fn):
+    key = next(_next_key)
+    with _callables_lock:
+        _callables[key] = fn
+    return ctypes.c_void_p(key)
+
+
+class Future:
+    """A reference to an ot_fmm_future (released on close / garbage collection)."""
+
+    def __init__(self, handle, executor):
+        self._h = handle
+        self.executor = executor  # keeps the executor alive while the future is
+
+    def then(self, fn):
+        _check(_lib.ot_fmm_future_then(self._h, _DISPATCH, _register(fn)), "ot_fmm_future_then")
+
+    def is_ready(self) -> bool:
+        r = ctypes.c_int()
+        _check(_lib.ot_fmm_future_is_ready(self._h, ctypes.byref(r)), "ot_fmm_future_is_ready")
+        return bool(r.value)
+
+    def wait(self, timeout=-1.0):
+        _check(_lib.ot_fmm_future_wait(self._h, float(timeout)), "ot_fmm_future_wait")
+
+    def set_ready(self):
+        _check(_lib.ot_fmm_future_set_ready(self._h), "ot_fmm_future_set_ready")
+
+    def close(self):
+        if self._h is not None:
+            _lib.ot_fmm_future_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Executor:
+    """Stream pool + task queue whose futures are completed by event polling."""
+
+    def __init__(self, nstreams=8, nworkers=0):
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(_lib.ot_fmm_executor_create(int(nstreams), int(nworkers), ctypes.byref(h)),
+               "ot_fmm_executor_create")
+        self._h = h
+
+    def close(self):
+        if self._h is not None:
+            _check(_lib.ot_fmm_executor_destroy(self._h), "ot_fmm_executor_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stream(self, i):
+        s = ctypes.c_void_p()
+        _check(_lib.ot_fmm_executor_stream(self._h, int(i), ctypes.byref(s)), "ot_fmm_executor_stream")
+        return s.value
+
+    def get_future(self, stream=None):
+        f = ctypes.c_void_p()
+        _check(_lib.ot_fmm_executor_get_future(self._h, _stream(stream), ctypes.byref(f)),
+               "ot_fmm_executor_get_future")
+        return Future(f, self)
+
+    def multipole_async(self, M, com, L):
+        f = ctypes.c_void_p()
+        _check(_lib.ot_fmm_executor_multipole_async(
+            self._h, _dptr(M, (20, 13824), "M"), _dptr(com, (3, 13824), "com"),
+            _dptr(L, (20, 512), "L"), ctypes.byref(f)), "ot_fmm_executor_multipole_async")
+        return Future(f, self)
+
+    def post(self, fn):
+        _check(_lib.ot_fmm_executor_post(self._h, _DISPATCH, _register(fn)), "ot_fmm_executor_post")
+
+    def poll(self) -> int:
+        n = ctypes.c_int()
+        _check(_lib.ot_fmm_executor_poll(self._h, ctypes.byref(n)), "ot_fmm_executor_poll")
+        return n.value
+
+    def outstanding(self) -> int:
+        n = ctypes.c_int64()
+        _check(_lib.ot_fmm_executor_outstanding(self._h, ctypes.byref(n)), "ot_fmm_executor_outstanding")
+        return n.value
+
+    def future(self):
+        """A host-side future, made ready by Future.set_ready()."""
+        f = ctypes.c_void_p()
+        _check(_lib.ot_fmm_future_create(self._h, ctypes.byref(f)), "ot_fmm_future_create")
+        return Future(f, self)

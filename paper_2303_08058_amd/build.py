@@ -11,7 +11,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "ot_fmm.hip"), os.path.join(HERE, "csrc", "ot_tree.hip")]
+SRC = [os.path.join(HERE, "csrc", "ot_fmm.hip"), os.path.join(HERE, "csrc", "ot_tree.hip"),
+       os.path.join(HERE, "csrc", "ot_async.hip")]
 HDR = os.path.join(ROOT, "include", "ot_fmm.h")
 LIB = os.path.join(HERE, "libotfmm.so")
 

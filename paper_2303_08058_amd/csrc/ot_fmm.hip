@@ -1064,6 +1064,7 @@ const char* ot_fmm_strerror(int code)
     case OT_FMM_EHIP: return "HIP runtime error";
     case OT_FMM_ENOMEM: return "device allocation failed";
     case OT_FMM_EUNSUPPORTED: return "unsupported device";
+    case OT_FMM_ETIMEDOUT: return "timed out";
     default: return "unknown error";
     }
 }

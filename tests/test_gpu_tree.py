@@ -323,3 +323,33 @@ def test_tree_passes_full_store_sampled(ot):
     torch.cuda.synchronize()
     check(F[:, s].cpu().numpy(), rF, AF, "evaluate F (sampled)")
     check(W[s].cpu().numpy(), rW, AW, "evaluate W (sampled)")
+
+
+# ---------------------------------------------------------------------------
+# interaction + evaluation on the GPU: momentum balance on a closed domain
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 8])
+def test_momentum_balance_closed_domain(ot, n):
+    """Open lattice with every sub-grid present: the criterion is symmetric
+    and so is availability, so with the total-order truncation the forces of
+    every interacting pair cancel and the total force vanishes to rounding.
+    Forward and evaluation both run on the GPU; n = 2 is also checked against
+    the oracle's forces."""
+    batch, M, X = synthetic.batched_config(n, 78 + n, periodic=False)
+    plan = ot.Plan.from_batch(batch)
+    N = batch["T"] * SUB3
+    L = _empty(20, N)
+    Md = _dev(M)
+    plan.multipole_batched(Md, _dev(X), L)
+    F, W = _empty(3, N), _empty(N)
+    ot.ot_fmm_evaluate(Md, L, F, W)
+    f = _host(F)
+    tot = f.sum(axis=1)
+    scale = np.abs(f).sum(axis=1)
+    print("n=%d: |sum F| / sum |F| = %s" % (n, np.abs(tot) / scale))
+    assert np.all(np.abs(tot) <= 1e-13 * scale)
+    w = _host(W)
+    if n == 2:
+        rF, rW = oracle.evaluate(M, oracle.batched_forward(batch, M, X))
+        assert np.allclose(f, rF, rtol=0, atol=1e-11 * np.abs(rF).max())
+        assert np.allclose(w, rW, rtol=0, atol=1e-11 * np.abs(rW).max())
