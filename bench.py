@@ -44,6 +44,8 @@ FLOP_PER_PAIR = {
 }
 
 
+SCHED_NAMES = {1: "W8", 2: "W16", 3: "W8P2"}
+
 # sources of the interaction kernels (the counter record names their hash)
 INTERACTION_SOURCES = ("ot_common.h", "ot_fmm.hip")
 
@@ -66,9 +68,11 @@ def measured_traffic(kernel, sched, n):
         h.update(open(os.path.join(ROOT, "paper_2303_08058_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    key = {"forward": "forward", "adjoint_source": "adjoint_source",
-           "adjoint_target": "adjoint_target"}[kernel]
-    key += "_w16" if (sched == 2 and kernel != "adjoint_source") else "_w8"
+    if kernel == "adjoint_source":
+        sched = sched >> 8
+    elif kernel == "adjoint_target":
+        sched = sched & 0xff
+    key = kernel + {1: "_w8", 2: "_w16", 3: "_w8p2"}[sched]
     k = rec["kernels"].get(key)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
@@ -123,7 +127,8 @@ def main():
     log("plan: %d targets, %d pairs" % (batch["T"], pairs))
 
     fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
-    log("autotuned schedules: forward %d, backward %d" % (fs, bs))
+    log("autotuned schedules: forward %s, adjoint target role %s, source role %s"
+        % (SCHED_NAMES[fs], SCHED_NAMES[bs & 0xff], SCHED_NAMES[bs >> 8]))
     plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
 
     # ------------------------------------------------------------ timed steps
@@ -169,7 +174,7 @@ def main():
 
     # copy of known size, for scaling HBM counters (not part of the step)
     if args.copy_calibration:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        a = torch.empty(1 << 28, dtype=torch.float64, device=dev)  # 2 GiB
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
@@ -209,7 +214,9 @@ def main():
                         "periodic, 20%% of sub-grids missing 1-9 neighbours, hipGraph step"
                         % (args.n, 8 * args.n),
             "subgrids": batch["S"], "cells": batch["S"] * 512, "pairs": pairs,
-            "field": batch["field"], "schedules": {"forward": fs, "backward": bs},
+            "field": batch["field"],
+            "schedules": {"forward": SCHED_NAMES[fs], "adjoint_target": SCHED_NAMES[bs & 0xff],
+                          "adjoint_source": SCHED_NAMES[bs >> 8]},
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -57,15 +57,21 @@ enum {
 };
 
 /* Schedules (how a target sub-grid's 512 cells are spread over wavefronts).
- * Both keep one work-group per target sub-grid and one staged source z-plane
- * in LDS; lanes are the 8x8 target cells of one z-plane. For the adjoint the
- * schedule applies to its target-role pass; the source-role pass always uses
- * 8 wavefronts. */
+ * All keep one work-group per target sub-grid and one staged source z-plane
+ * in LDS; lanes are the 8x8 target cells of one z-plane.
+ * The adjoint takes two: sched = target_role | (source_role << 8)
+ * (OT_FMM_SCHED_BWD); the target-role pass accepts every schedule, the
+ * source-role pass AUTO, W8 or W8P2 (its accumulators do not fit 16
+ * wavefronts). A byte left AUTO takes the plan's tuned choice, else W16 for
+ * the target role and W8 for the source role. */
 enum {
     OT_FMM_SCHED_AUTO = 0,  /* the plan's tuned choice (ot_fmm_autotune), else W16 */
     OT_FMM_SCHED_W8 = 1,    /* 8 wavefronts: one per target z-plane */
-    OT_FMM_SCHED_W16 = 2    /* 16 wavefronts: two per target z-plane, stencil rows split */
+    OT_FMM_SCHED_W16 = 2,   /* 16 wavefronts: two per target z-plane, stencil rows split */
+    OT_FMM_SCHED_W8P2 = 3   /* 8 wavefronts, two passes over the source planes (target
+                               planes 0-3, then 4-7), two wavefronts per target plane */
 };
+#define OT_FMM_SCHED_BWD(target_role, source_role) ((target_role) | ((source_role) << 8))
 
 /* ---------------------------------------------------------------------------
  * Single sub-grid forms (one 24^3 halo block = 3x3x3 sub-grids, all present).

@@ -34,6 +34,12 @@ OT_FMM_ETIMEDOUT = -5
 SCHED_AUTO = 0
 SCHED_W8 = 1
 SCHED_W16 = 2
+SCHED_W8P2 = 3
+
+
+def sched_bwd(target_role=SCHED_AUTO, source_role=SCHED_AUTO):
+    """Backward schedule: target-role pass in the low byte, source-role pass in the next."""
+    return int(target_role) | (int(source_role) << 8)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

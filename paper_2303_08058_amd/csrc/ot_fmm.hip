@@ -482,11 +482,12 @@ struct Layout {
     static constexpr int stride = (nvec % 2 == 1) ? 2 * nvec : 2 * nvec + 2;  // doubles per cell
 };
 
-template <int MODE, int NW, bool SPLIT>
+template <int MODE, int NW, bool SPLIT, int NP>
 constexpr int lds_doubles()
 {
     constexpr int plane = Layout<MODE>::stride * kPlane;
-    constexpr int merge = SPLIT ? NW * ModeTraits<MODE>::nacc * 64 : ((NW == 16) ? 20 * kSub3 : 0);
+    constexpr int merge =
+        SPLIT ? NW * ModeTraits<MODE>::nacc * 64 : ((NW == 16 || NP == 2) ? 20 * kSub3 : 0);
     return plane > merge ? plane : merge;
 }
 
@@ -621,26 +622,38 @@ __device__ __forceinline__ void stage_store(const PlaneLoad<MODE, NW>& pl, const
 // block; its NW wavefronts share the plane's 64 cells and take the stencil
 // rows round-robin; only the 19 source planes within reach are staged, and the
 // partial sums are added in a fixed order at the end.
-template <int MODE, int NW, bool SPLIT>
+// NP = 2 (8 wavefronts): two passes over the source planes, target planes
+// 0-3 then 4-7, two wavefronts per target plane with its stencil rows split
+// in halves as with 16 wavefronts. Each pass stages the 21 source planes in
+// its reach (42 instead of 24), and in exchange the work per staged plane is
+// spread evenly over the 4 SIMDs (about 95% against 86% for one pass with a
+// wavefront per target plane).
+template <int MODE, int NW, bool SPLIT, int NP>
 __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
 {
     using T = ModeTraits<MODE>;
     using Lay = Layout<MODE>;
     static_assert(NW == 8 || NW == 16, "8 or 16 wavefronts");
-    static_assert(!SPLIT || (T::halo && NW == 8), "plane split: single-block forms, 8 wavefronts");
-    __shared__ double lds[lds_doubles<MODE, NW, SPLIT>()];
+    static_assert(!SPLIT || (T::halo && NW == 8 && NP == 1), "plane split: single-block forms, 8 wavefronts");
+    static_assert(NP == 1 || (NP == 2 && NW == 8), "two passes: 8 wavefronts");
+    constexpr bool HALVES = !SPLIT && (NW == 16 || NP == 2);  // two wavefronts per target plane
+    __shared__ double lds[lds_doubles<MODE, NW, SPLIT, NP>()];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int owner = SPLIT ? 0 : (p.order ? p.order[blockIdx.x] : (int)blockIdx.x);
     const int4* s_rel = T::halo ? nullptr : p.rel + (long)owner * 27;  // this owner's relations
-    // With 8 wavefronts (wave w on SIMD w % 4) the target planes are paired per
-    // SIMD as (0,4) (1,6) (2,5) (3,7): the pairing whose summed per-plane work
-    // varies least from one staged plane to the next.
+    const int half = HALVES ? (wave & 1) : 0;
+#pragma unroll 1
+    for (int pass = 0; pass < NP; ++pass) {
+    // With 8 wavefronts and one pass (wave w on SIMD w % 4) the target planes
+    // are paired per SIMD as (0,4) (1,6) (2,5) (3,7): the pairing whose summed
+    // per-plane work varies least from one staged plane to the next.
     const int zt = SPLIT ? (int)blockIdx.x
-                         : ((NW == 16) ? (wave >> 1) : (wave == 5 ? 6 : (wave == 6 ? 5 : wave)));
-    const int half = (!SPLIT && NW == 16) ? (wave & 1) : 0;
+                 : (NW == 16) ? (wave >> 1)
+                 : (NP == 2) ? 4 * pass + (wave >> 1)
+                             : (wave == 5 ? 6 : (wave == 6 ? 5 : wave));
     const int xt = lane & 7, yt = lane >> 3;
     const int pz = zt & 1;
     const int cell = xt + 8 * yt + 64 * zt;
@@ -672,8 +685,10 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     const int step_y = sgy * kHalo * cs;
     const double2* lds2 = reinterpret_cast<const double2*>(lds);
 
-    const int zs_begin = SPLIT ? (8 + zt - kReach > 0 ? 8 + zt - kReach : 0) : 0;
-    const int zs_end = SPLIT ? (8 + zt + kReach + 1 < kHalo ? 8 + zt + kReach + 1 : kHalo) : kHalo;
+    const int zs_begin = SPLIT ? (8 + zt - kReach > 0 ? 8 + zt - kReach : 0)
+                       : (NP == 2 ? (pass == 0 ? 0 : 8 + 4 - kReach) : 0);
+    const int zs_end = SPLIT ? (8 + zt + kReach + 1 < kHalo ? 8 + zt + kReach + 1 : kHalo)
+                     : (NP == 2 ? (pass == 0 ? 8 + 3 + kReach + 1 : kHalo) : kHalo);
     // the next plane's loads are issued as soon as a wavefront is done with
     // the current one, so they overlap the barrier wait
     for (int zs = zs_begin; zs < zs_end; ++zs) {
@@ -691,7 +706,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
             if (SPLIT) {
                 r0 += wave;
                 rstep = NW;
-            } else if (NW == 16) {
+            } else if (HALVES) {
                 if (half == 0)
                     r1 = rg[1];
                 else
@@ -756,7 +771,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
             for (int w = 1; w < NW; ++w) v += lds[(w * T::nacc + a) * 64 + lane];
             acc[a] = v;
         }
-    } else if constexpr (NW == 16) {
+    } else if constexpr (HALVES) {
         // the two wavefronts of a target plane add their partial sums, through
         // LDS in rounds of at most 20 components
 #pragma unroll
@@ -772,7 +787,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
                 for (int a = a0; a < T::nacc && a < a0 + 20; ++a) acc[a] += lds[(a - a0) * kSub3 + cell];
             }
         }
-        if (half == 1) return;
+        if (half == 1) continue;  // the next pass (none after the last)
     }
     if constexpr (!T::adjoint) {
         double L[20];
@@ -822,6 +837,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
             for (int k = 0; k < 3; ++k) p.out0[k * p.out_stride + ob] += gx[k];
         }
     }
+    }  // pass
 }
 
 }  // namespace
@@ -865,14 +881,26 @@ int ensure_device()
 namespace {
 
 
-template <int MODE, int NW, bool SPLIT = false>
+template <int MODE, int NW, bool SPLIT = false, int NP = 1>
 int launch(const KParams& kp, int nblocks, hipStream_t stream)
 {
     if (nblocks <= 0) return OT_FMM_OK;
-    hipLaunchKernelGGL((k_interact<MODE, NW, SPLIT>), dim3(nblocks), dim3(NW * 64), 0, stream, kp);
+    hipLaunchKernelGGL((k_interact<MODE, NW, SPLIT, NP>), dim3(nblocks), dim3(NW * 64), 0, stream, kp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return OT_FMM_OK;
+}
+
+constexpr int kDefaultSourceSched = OT_FMM_SCHED_W8;
+
+bool valid_fwd_sched(int s) { return s >= OT_FMM_SCHED_AUTO && s <= OT_FMM_SCHED_W8P2; }
+
+// target role: any forward schedule; source role: AUTO, W8 or W8P2
+bool valid_bwd_sched(int s)
+{
+    const int t = s & 0xff, r = s >> 8;
+    return s >= 0 && valid_fwd_sched(t) &&
+           (r == OT_FMM_SCHED_AUTO || r == OT_FMM_SCHED_W8 || r == OT_FMM_SCHED_W8P2);
 }
 
 int pick_fwd(int sched, int tuned)
@@ -931,13 +959,13 @@ int timing_end(const std::pair<hipEvent_t, hipEvent_t>& ev, hipStream_t stream)
     return OT_FMM_OK;
 }
 
-template <int MODE, int NW>
+template <int MODE, int NW, int NP = 1>
 int launch_timed(ot_fmm_plan plan, int which, const KParams& kp, int nblocks, hipStream_t stream)
 {
     std::pair<hipEvent_t, hipEvent_t> ev;
     int rc = timing_begin(plan, which, stream, &ev);
     if (rc) return rc;
-    rc = launch<MODE, NW>(kp, nblocks, stream);
+    rc = launch<MODE, NW, false, NP>(kp, nblocks, stream);
     if (rc) return rc;
     return timing_end(ev, stream);
 }
@@ -960,15 +988,21 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
     sched = pick_fwd(sched, plan->tuned_fwd);
     if (sched == OT_FMM_SCHED_W8) return launch_timed<MODE_FWD_STORE, 8>(plan, 0, kp, plan->T, stream);
     if (sched == OT_FMM_SCHED_W16) return launch_timed<MODE_FWD_STORE, 16>(plan, 0, kp, plan->T, stream);
+    if (sched == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_FWD_STORE, 8, 2>(plan, 0, kp, plan->T, stream);
     return fail(OT_FMM_EINVAL, "unknown forward schedule");
 }
 
 int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
                 double* gM, double* gcom, int sched, hipStream_t stream)
 {
-    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_bwd ? plan->tuned_bwd : OT_FMM_SCHED_W16;
-    if (sched != OT_FMM_SCHED_W8 && sched != OT_FMM_SCHED_W16)
-        return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    // target-role schedule in the low byte, source-role schedule in the next
+    int tsched = sched & 0xff, ssched = (sched >> 8) & 0xff;
+    if (tsched == OT_FMM_SCHED_AUTO)
+        tsched = (plan->tuned_bwd & 0xff) ? (plan->tuned_bwd & 0xff) : OT_FMM_SCHED_W16;
+    if (ssched == OT_FMM_SCHED_AUTO)
+        ssched = (plan->tuned_bwd >> 8) ? (plan->tuned_bwd >> 8) : kDefaultSourceSched;
+    if (!valid_bwd_sched(tsched | (ssched << 8))) return fail(OT_FMM_EINVAL, "unknown backward schedule");
     const long NS = (long)plan->S * kSub3, NT = (long)plan->T * kSub3;
     // source role: owners are store sub-grids, sources the target cells that see them
     KParams b2{};
@@ -986,7 +1020,10 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b2.out_stride = NS;
     b2.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) b2.period[k] = plan->period[k];
-    int rc = launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, stream);
+    // the source-role pass has 8 wavefronts (its 40 accumulators do not fit
+    // the register budget of 16): one pass, or two with split rows
+    int rc = ssched == OT_FMM_SCHED_W8P2 ? launch_timed<MODE_B2_STORE, 8, 2>(plan, 1, b2, plan->S, stream)
+                                         : launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, stream);
     if (rc) return rc;
     // target role: owners are targets, sources their neighbours' cells
     KParams b1{};
@@ -1003,9 +1040,8 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b1.out_stride = NS;
     b1.out_blk = plan->d_tgt;
     for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
-    // the source-role pass keeps 8 wavefronts (its 40 accumulators do not fit
-    // the register budget of 16); the target-role pass follows the schedule
-    if (sched == OT_FMM_SCHED_W16) return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, stream);
+    if (tsched == OT_FMM_SCHED_W16) return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, stream);
+    if (tsched == OT_FMM_SCHED_W8P2) return launch_timed<MODE_B1_STORE, 8, 2>(plan, 2, b1, plan->T, stream);
     return launch_timed<MODE_B1_STORE, 8>(plan, 2, b1, plan->T, stream);
 }
 
@@ -1209,7 +1245,7 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
     if (rc) return rc;
     if (!aligned16(M) || !aligned16(com) || !aligned16(L))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
-    if (sched < 0 || sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
+    if (!valid_fwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
     return fwd_batched(plan, M, com, L, sched, (hipStream_t)stream);
 }
 
@@ -1224,7 +1260,7 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
     if (gM == M || gM == gL || gcom == com || (const double*)gcom == gL || (const double*)gM == com)
         return fail(OT_FMM_EINVAL, "outputs alias inputs");
-    if (sched < 0 || sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    if (!valid_bwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown backward schedule");
     return bwd_batched(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
 }
 
@@ -1257,7 +1293,7 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
     };
     int best_f = OT_FMM_SCHED_W16;
     float best_ms = 3.0e38f;
-    for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16}) {
+    for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2}) {
         float ms = 0.0f;
         rc = time_it([&] { return fwd_batched(plan, M, com, L, cand, s); }, &ms);
         if (rc) break;
@@ -1266,16 +1302,31 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
             best_f = cand;
         }
     }
-    int best_b = OT_FMM_SCHED_W16;
+    int best_b = OT_FMM_SCHED_W16 | (kDefaultSourceSched << 8);
     if (!rc && with_bwd) {
+        // source role first (target role W16), then the target role with it
         best_ms = 3.0e38f;
-        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16}) {
+        int best_src = kDefaultSourceSched;
+        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2}) {
             float ms = 0.0f;
-            rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, cand, s); }, &ms);
+            const int sc = OT_FMM_SCHED_W16 | (cand << 8);
+            rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, sc, s); }, &ms);
             if (rc) break;
             if (ms < best_ms) {
                 best_ms = ms;
-                best_b = cand;
+                best_src = cand;
+                best_b = sc;
+            }
+        }
+        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2}) {
+            if (rc) break;
+            float ms = 0.0f;
+            const int sc = cand | (best_src << 8);
+            rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, sc, s); }, &ms);
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_b = sc;
             }
         }
     }
@@ -1301,8 +1352,8 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     const bool with_bwd = gL || gM || gcom;
     if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
-    if (fwd_sched < 0 || fwd_sched > OT_FMM_SCHED_W16) return fail(OT_FMM_EINVAL, "unknown schedule");
-    if (with_bwd && (bwd_sched < 0 || bwd_sched > OT_FMM_SCHED_W16))
+    if (!valid_fwd_sched(fwd_sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
+    if (with_bwd && !valid_bwd_sched(bwd_sched))
         return fail(OT_FMM_EINVAL, "unknown backward schedule");
     hipStream_t cs;
     OT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));

@@ -57,7 +57,7 @@ def test_multipole_single_block(ot):
     print("multipole worst", assert_parity(_host(L), ref, TOL, what="multipole"))
 
 
-@pytest.mark.parametrize("sched", [1, 2])
+@pytest.mark.parametrize("sched", [1, 2, 3])
 def test_batched_small_periodic_with_missing(ot, sched):
     batch, M, X = synthetic.batched_config(2, 21, missing_frac=0.5)
     ref = oracle.batched_forward(batch, M, X)
@@ -126,7 +126,8 @@ def _small_adjoint_case():
     return batch, M, X
 
 
-@pytest.mark.parametrize("sched", [1, 2])
+# (target-role schedule, source-role schedule)
+@pytest.mark.parametrize("sched", [(1, 1), (2, 1), (3, 3), (2, 3)])
 def test_backward_small_open(ot, sched):
     batch, M, X = _small_adjoint_case()
     w = synthetic.weights(batch["T"], 42)
@@ -134,7 +135,7 @@ def test_backward_small_open(ot, sched):
     plan = ot.Plan.from_batch(batch)
     gM = _empty(20, 27 * 512)
     gX = _empty(3, 27 * 512)
-    plan.multipole_backward(_dev(M), _dev(X), _dev(w), gM, gX, sched=sched)
+    plan.multipole_backward(_dev(M), _dev(X), _dev(w), gM, gX, sched=ot.sched_bwd(*sched))
     print("gM worst", assert_parity(_host(gM), gM_ref, TOL, what="gM"))
     print("gX worst", assert_parity(_host(gX), gX_ref, TOL, what="gX"))
 
@@ -225,7 +226,7 @@ def test_autotune_choices_are_valid_and_exact(ot):
     Md, Xd = _dev(M), _dev(X)
     L = _empty(20, batch["T"] * 512)
     f, b = plan.autotune(Md, Xd, L)
-    assert f in (1, 2) and b in (1, 2)
+    assert f in (1, 2, 3) and (b & 0xff) in (1, 2, 3) and (b >> 8) in (1, 3)
     plan.multipole_batched(Md, Xd, L)   # AUTO -> tuned
     ref = oracle.batched_forward(batch, M, X, tsel=[0, 5, 26])
     got = _host(L).reshape(20, 27, 512)[:, [0, 5, 26]].reshape(20, -1)
@@ -238,6 +239,10 @@ def test_invalid_schedule_rejected(ot):
     L = _empty(20, batch["T"] * 512)
     with pytest.raises(ot.OtFmmError):
         plan.multipole_batched(_dev(M), _dev(X), L, sched=7)
+    gM, gX = _empty(20, batch["S"] * 512), _empty(3, batch["S"] * 512)
+    for bad in (ot.sched_bwd(2, 2), ot.sched_bwd(4, 1), 1 << 16):  # no 16-wavefront source role
+        with pytest.raises(ot.OtFmmError):
+            plan.multipole_backward(_dev(M), _dev(X), L, gM, gX, sched=bad)
 
 
 # ---------------------------------------------------------------------------
@@ -256,7 +261,7 @@ def _cols(a, sel):
     return a.reshape(a.shape[0], -1, 512)[:, sel].reshape(a.shape[0], -1)
 
 
-@pytest.mark.parametrize("sched", [1, 2])
+@pytest.mark.parametrize("sched", [1, 2, 3])
 def test_config3_forward_sampled(ot, sched):
     """16^3 sub-grids, periodic, 15% missing 1-9 neighbours: every output of
     the launch is produced, a seeded sample of targets (half of them with
