@@ -44,7 +44,10 @@ FLOP_PER_PAIR = {
 }
 
 
-SCHED_NAMES = {1: "W8", 2: "W16", 3: "W8P2"}
+def sched_name(s):
+    """Name of a one-pass schedule code (shape, optionally + persistent)."""
+    base = {1: "W8", 2: "W16", 3: "W8P2"}[s & 0xF]
+    return base + ("+persistent" if s & 0x10 else "")
 
 # sources of the interaction kernels (the counter record names their hash)
 INTERACTION_SOURCES = ("ot_common.h", "ot_fmm.hip")
@@ -72,7 +75,7 @@ def measured_traffic(kernel, sched, n):
         sched = sched >> 8
     elif kernel == "adjoint_target":
         sched = sched & 0xff
-    key = kernel + {1: "_w8", 2: "_w16", 3: "_w8p2"}[sched]
+    key = kernel + {1: "_w8", 2: "_w16", 3: "_w8p2"}[sched & 0xF] + ("_persistent" if sched & 0x10 else "")
     k = rec["kernels"].get(key)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
@@ -128,7 +131,7 @@ def main():
 
     fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
     log("autotuned schedules: forward %s, adjoint target role %s, source role %s"
-        % (SCHED_NAMES[fs], SCHED_NAMES[bs & 0xff], SCHED_NAMES[bs >> 8]))
+        % (sched_name(fs), sched_name(bs & 0xff), sched_name(bs >> 8)))
     plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
 
     # ------------------------------------------------------------ timed steps
@@ -215,8 +218,8 @@ def main():
                         % (args.n, 8 * args.n),
             "subgrids": batch["S"], "cells": batch["S"] * 512, "pairs": pairs,
             "field": batch["field"],
-            "schedules": {"forward": SCHED_NAMES[fs], "adjoint_target": SCHED_NAMES[bs & 0xff],
-                          "adjoint_source": SCHED_NAMES[bs >> 8]},
+            "schedules": {"forward": sched_name(fs), "adjoint_target": sched_name(bs & 0xff),
+                          "adjoint_source": sched_name(bs >> 8)},
             "parallelism": "single GPU",
         },
         "roofline": {

@@ -68,8 +68,13 @@ enum {
     OT_FMM_SCHED_AUTO = 0,  /* the plan's tuned choice (ot_fmm_autotune), else W16 */
     OT_FMM_SCHED_W8 = 1,    /* 8 wavefronts: one per target z-plane */
     OT_FMM_SCHED_W16 = 2,   /* 16 wavefronts: two per target z-plane, stencil rows split */
-    OT_FMM_SCHED_W8P2 = 3   /* 8 wavefronts, two passes over the source planes (target
+    OT_FMM_SCHED_W8P2 = 3,  /* 8 wavefronts, two passes over the source planes (target
                                planes 0-3, then 4-7), two wavefronts per target plane */
+    /* flag, OR-ed into a schedule: persistent launch -- as many work-groups as
+     * are resident at once, taking work-list entries (longest first) from a
+     * counter that a one-thread kernel zeroes just before; up to 64 such
+     * launches of one plan may be in flight at once */
+    OT_FMM_SCHED_PERSISTENT = 0x10
 };
 #define OT_FMM_SCHED_BWD(target_role, source_role) ((target_role) | ((source_role) << 8))
 

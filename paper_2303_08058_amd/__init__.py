@@ -35,6 +35,7 @@ SCHED_AUTO = 0
 SCHED_W8 = 1
 SCHED_W16 = 2
 SCHED_W8P2 = 3
+SCHED_PERSISTENT = 0x10  # flag OR-ed into a schedule
 
 
 def sched_bwd(target_role=SCHED_AUTO, source_role=SCHED_AUTO):

@@ -38,6 +38,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -452,6 +453,8 @@ struct KParams {
     long out_stride;
     const int* out_blk;    // owner -> output block (NULL: identity)
     double period[3];
+    int* counter;          // persistent launch: work counter, zeroed before the launch
+    int n_items;           // persistent launch: number of work-list entries
 };
 
 template <int MODE>
@@ -628,7 +631,7 @@ __device__ __forceinline__ void stage_store(const PlaneLoad<MODE, NW>& pl, const
 // its reach (42 instead of 24), and in exchange the work per staged plane is
 // spread evenly over the 4 SIMDs (about 95% against 86% for one pass with a
 // wavefront per target plane).
-template <int MODE, int NW, bool SPLIT, int NP>
+template <int MODE, int NW, bool SPLIT, int NP, bool PERSIST>
 __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
 {
     using T = ModeTraits<MODE>;
@@ -642,9 +645,25 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int owner = SPLIT ? 0 : (p.order ? p.order[blockIdx.x] : (int)blockIdx.x);
-    const int4* s_rel = T::halo ? nullptr : p.rel + (long)owner * 27;  // this owner's relations
     const int half = HALVES ? (wave & 1) : 0;
+    // Persistent launch (counter != NULL): the work-group takes work-list
+    // entries from a global counter until the list is exhausted; otherwise it
+    // does the one entry of its index.
+    __shared__ int s_item;
+    static_assert(!PERSIST || !T::halo, "persistent launches: batched forms");
+    constexpr bool persistent = PERSIST;
+    int item = (int)blockIdx.x;
+#pragma unroll 1
+    for (;;) {
+    if (persistent) {
+        __syncthreads();  // the previous entry is finished by every wavefront
+        if (tid == 0) s_item = atomicAdd(p.counter, 1);
+        __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= p.n_items) break;
+    }
+    const int owner = SPLIT ? 0 : (p.order ? p.order[item] : item);
+    const int4* s_rel = T::halo ? nullptr : p.rel + (long)owner * 27;  // this owner's relations
 #pragma unroll 1
     for (int pass = 0; pass < NP; ++pass) {
     // With 8 wavefronts and one pass (wave w on SIMD w % 4) the target planes
@@ -838,7 +857,11 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         }
     }
     }  // pass
+    if (!persistent) break;
+    }  // work-list entries
 }
+
+__global__ void k_zero_counter(int* c) { *c = 0; }
 
 }  // namespace
 
@@ -881,11 +904,12 @@ int ensure_device()
 namespace {
 
 
-template <int MODE, int NW, bool SPLIT = false, int NP = 1>
+template <int MODE, int NW, bool SPLIT = false, int NP = 1, bool PERSIST = false>
 int launch(const KParams& kp, int nblocks, hipStream_t stream)
 {
     if (nblocks <= 0) return OT_FMM_OK;
-    hipLaunchKernelGGL((k_interact<MODE, NW, SPLIT, NP>), dim3(nblocks), dim3(NW * 64), 0, stream, kp);
+    hipLaunchKernelGGL((k_interact<MODE, NW, SPLIT, NP, PERSIST>), dim3(nblocks), dim3(NW * 64), 0, stream,
+                       kp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return OT_FMM_OK;
@@ -893,15 +917,26 @@ int launch(const KParams& kp, int nblocks, hipStream_t stream)
 
 constexpr int kDefaultSourceSched = OT_FMM_SCHED_W8;
 
-bool valid_fwd_sched(int s) { return s >= OT_FMM_SCHED_AUTO && s <= OT_FMM_SCHED_W8P2; }
+// a shape (W8, W16, W8P2), optionally with the persistent flag; or AUTO alone
+bool valid_fwd_sched(int s)
+{
+    if (s == OT_FMM_SCHED_AUTO) return true;
+    const int shape = s & ~OT_FMM_SCHED_PERSISTENT;
+    return s > 0 && s <= (OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT) && shape >= OT_FMM_SCHED_W8 &&
+           shape <= OT_FMM_SCHED_W8P2;
+}
 
-// target role: any forward schedule; source role: AUTO, W8 or W8P2
+// target role: any forward schedule; source role: AUTO, W8 or W8P2 (either
+// optionally persistent)
 bool valid_bwd_sched(int s)
 {
+    if (s < 0 || (s >> 16) != 0) return false;
     const int t = s & 0xff, r = s >> 8;
-    return s >= 0 && valid_fwd_sched(t) &&
-           (r == OT_FMM_SCHED_AUTO || r == OT_FMM_SCHED_W8 || r == OT_FMM_SCHED_W8P2);
+    const int rshape = r & ~OT_FMM_SCHED_PERSISTENT;
+    return valid_fwd_sched(t) && valid_fwd_sched(r) && rshape != OT_FMM_SCHED_W16;
 }
+
+constexpr int kCounterSlots = 64;
 
 int pick_fwd(int sched, int tuned)
 {
@@ -923,6 +958,10 @@ struct ot_fmm_plan_s {
     int* d_fwd_order = nullptr; // [T]
     int* d_rev_order = nullptr; // [S]
     int tuned_fwd = 0, tuned_bwd = 0;
+    // persistent launches: one work counter per launch in flight (rotating)
+    int* d_counters = nullptr;  // [kCounterSlots]
+    std::atomic<unsigned> next_counter{0};
+    int n_cu = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // per-kernel timing (forward, adjoint source pass, adjoint target pass)
@@ -959,13 +998,42 @@ int timing_end(const std::pair<hipEvent_t, hipEvent_t>& ev, hipStream_t stream)
     return OT_FMM_OK;
 }
 
+// Work-groups of one instantiation resident per CU (LDS and registers), from
+// the runtime's occupancy calculator, computed once.
+template <int MODE, int NW, int NP>
+int resident_per_cu()
+{
+    static const int n = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_interact<MODE, NW, false, NP, true>, NW * 64, 0) !=
+                hipSuccess ||
+            b < 1)
+            b = 1;
+        return b;
+    }();
+    return n;
+}
+
+// One launch over `nblocks` work-list entries: a work-group per entry, or
+// (persistent) as many work-groups as fit the device at once, each taking
+// entries from a zeroed counter slot of the plan.
 template <int MODE, int NW, int NP = 1>
-int launch_timed(ot_fmm_plan plan, int which, const KParams& kp, int nblocks, hipStream_t stream)
+int launch_timed(ot_fmm_plan plan, int which, KParams kp, int nblocks, bool persistent,
+                 hipStream_t stream)
 {
     std::pair<hipEvent_t, hipEvent_t> ev;
     int rc = timing_begin(plan, which, stream, &ev);
     if (rc) return rc;
-    rc = launch<MODE, NW, false, NP>(kp, nblocks, stream);
+    if (persistent && nblocks > 0) {
+        int* c = plan->d_counters + plan->next_counter.fetch_add(1) % kCounterSlots;
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, stream, c);
+        kp.counter = c;
+        kp.n_items = nblocks;
+        const long resident = (long)plan->n_cu * resident_per_cu<MODE, NW, NP>();
+        nblocks = (int)std::min<long>(nblocks, resident);
+    }
+    rc = persistent ? launch<MODE, NW, false, NP, true>(kp, nblocks, stream)
+                    : launch<MODE, NW, false, NP, false>(kp, nblocks, stream);
     if (rc) return rc;
     return timing_end(ev, stream);
 }
@@ -986,10 +1054,13 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
     kp.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
     sched = pick_fwd(sched, plan->tuned_fwd);
-    if (sched == OT_FMM_SCHED_W8) return launch_timed<MODE_FWD_STORE, 8>(plan, 0, kp, plan->T, stream);
-    if (sched == OT_FMM_SCHED_W16) return launch_timed<MODE_FWD_STORE, 16>(plan, 0, kp, plan->T, stream);
-    if (sched == OT_FMM_SCHED_W8P2)
-        return launch_timed<MODE_FWD_STORE, 8, 2>(plan, 0, kp, plan->T, stream);
+    const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
+    const int shape = sched & ~OT_FMM_SCHED_PERSISTENT;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FWD_STORE, 8>(plan, 0, kp, plan->T, pers, stream);
+    if (shape == OT_FMM_SCHED_W16)
+        return launch_timed<MODE_FWD_STORE, 16>(plan, 0, kp, plan->T, pers, stream);
+    if (shape == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_FWD_STORE, 8, 2>(plan, 0, kp, plan->T, pers, stream);
     return fail(OT_FMM_EINVAL, "unknown forward schedule");
 }
 
@@ -1022,8 +1093,10 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     for (int k = 0; k < 3; ++k) b2.period[k] = plan->period[k];
     // the source-role pass has 8 wavefronts (its 40 accumulators do not fit
     // the register budget of 16): one pass, or two with split rows
-    int rc = ssched == OT_FMM_SCHED_W8P2 ? launch_timed<MODE_B2_STORE, 8, 2>(plan, 1, b2, plan->S, stream)
-                                         : launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, stream);
+    const bool spers = (ssched & OT_FMM_SCHED_PERSISTENT) != 0;
+    int rc = (ssched & ~OT_FMM_SCHED_PERSISTENT) == OT_FMM_SCHED_W8P2
+                 ? launch_timed<MODE_B2_STORE, 8, 2>(plan, 1, b2, plan->S, spers, stream)
+                 : launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, spers, stream);
     if (rc) return rc;
     // target role: owners are targets, sources their neighbours' cells
     KParams b1{};
@@ -1040,9 +1113,13 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b1.out_stride = NS;
     b1.out_blk = plan->d_tgt;
     for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
-    if (tsched == OT_FMM_SCHED_W16) return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, stream);
-    if (tsched == OT_FMM_SCHED_W8P2) return launch_timed<MODE_B1_STORE, 8, 2>(plan, 2, b1, plan->T, stream);
-    return launch_timed<MODE_B1_STORE, 8>(plan, 2, b1, plan->T, stream);
+    const bool tpers = (tsched & OT_FMM_SCHED_PERSISTENT) != 0;
+    const int tshape = tsched & ~OT_FMM_SCHED_PERSISTENT;
+    if (tshape == OT_FMM_SCHED_W16)
+        return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, tpers, stream);
+    if (tshape == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_B1_STORE, 8, 2>(plan, 2, b1, plan->T, tpers, stream);
+    return launch_timed<MODE_B1_STORE, 8>(plan, 2, b1, plan->T, tpers, stream);
 }
 
 int check_plan(ot_fmm_plan plan)
@@ -1071,6 +1148,7 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_tgt);
     (void)hipFree(p->d_fwd_order);
     (void)hipFree(p->d_rev_order);
+    (void)hipFree(p->d_counters);
 }
 
 // Work order: longest work first (a greedy longest-processing-time list for
@@ -1209,9 +1287,16 @@ int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
     if (period)
         for (int k = 0; k < 3; ++k) p->period[k] = period[k];
     p->pairs = pairs;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, p->device)) != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    p->n_cu = prop.multiProcessorCount;
+    const std::vector<int> zeros(kCounterSlots, 0);
     if ((rc = upload(&p->d_fwd_rel, fwd)) || (rc = upload(&p->d_rev_rel, rev)) ||
         (rc = upload(&p->d_tgt, tg)) || (rc = upload(&p->d_fwd_order, fo)) ||
-        (rc = upload(&p->d_rev_order, ro))) {
+        (rc = upload(&p->d_rev_order, ro)) || (rc = upload(&p->d_counters, zeros))) {
         free_plan_memory(p);
         delete p;
         return rc;
@@ -1291,44 +1376,41 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
         OT_HIP(hipEventElapsedTime(ms, e0, e1));
         return OT_FMM_OK;
     };
+    // forward: every shape, then the winner as a persistent launch
     int best_f = OT_FMM_SCHED_W16;
     float best_ms = 3.0e38f;
-    for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2}) {
+    auto try_fwd = [&](int cand) -> int {
         float ms = 0.0f;
-        rc = time_it([&] { return fwd_batched(plan, M, com, L, cand, s); }, &ms);
-        if (rc) break;
-        if (ms < best_ms) {
+        int r = time_it([&] { return fwd_batched(plan, M, com, L, cand, s); }, &ms);
+        if (!r && ms < best_ms) {
             best_ms = ms;
             best_f = cand;
         }
-    }
+        return r;
+    };
+    for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2})
+        if ((rc = try_fwd(cand))) break;
+    if (!rc) rc = try_fwd(best_f | OT_FMM_SCHED_PERSISTENT);
     int best_b = OT_FMM_SCHED_W16 | (kDefaultSourceSched << 8);
     if (!rc && with_bwd) {
         // source role first (target role W16), then the target role with it
         best_ms = 3.0e38f;
-        int best_src = kDefaultSourceSched;
-        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2}) {
+        auto try_bwd = [&](int sc) -> int {
             float ms = 0.0f;
-            const int sc = OT_FMM_SCHED_W16 | (cand << 8);
-            rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, sc, s); }, &ms);
-            if (rc) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best_src = cand;
-                best_b = sc;
-            }
-        }
-        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2}) {
-            if (rc) break;
-            float ms = 0.0f;
-            const int sc = cand | (best_src << 8);
-            rc = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, sc, s); }, &ms);
-            if (rc) break;
-            if (ms < best_ms) {
+            int r = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, sc, s); }, &ms);
+            if (!r && ms < best_ms) {
                 best_ms = ms;
                 best_b = sc;
             }
-        }
+            return r;
+        };
+        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
+            if ((rc = try_bwd(OT_FMM_SCHED_W16 | (cand << 8)))) break;
+        if (!rc) rc = try_bwd(best_b | (OT_FMM_SCHED_PERSISTENT << 8));
+        const int src = best_b >> 8;
+        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
+            if (!rc) rc = try_bwd(cand | (src << 8));
+        if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_PERSISTENT);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -118,7 +118,8 @@ __device__ __forceinline__ double quad_sum(double v)
 // four lanes then stores 5 of the 20 parent moments.
 __global__ void __launch_bounds__(256) k_m2m(const TreeParams p)
 {
-    const long w = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    // wave index, kept in scalar registers so that the child lookup is a scalar load
+    const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (w >= (long)p.Sp * 32) return;  // whole wavefronts: 8 octants x 4 z-pairs per parent
     const int lane = threadIdx.x & 63;
     const int node = (int)(w >> 5), o = (int)((w >> 2) & 7), Z = (int)(w & 3);
@@ -126,34 +127,33 @@ __global__ void __launch_bounds__(256) k_m2m(const TreeParams p)
     const long j1 = j0 + 64;
     const long nc = p.n_child;
 
-    const double m0 = p.m_in[j0], m1 = p.m_in[j1];
-    double x0[3], x1[3], c[3];
+    // every load of the wavefront is issued before the first use
+    double m0[20], m1[20], x0[3], x1[3], c[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         x0[k] = p.x_in[k * nc + j0];
         x1[k] = p.x_in[k * nc + j1];
     }
-    const double m = quad_sum(m0 + m1);
+#pragma unroll
+    for (int b = 0; b < 20; ++b) {
+        m0[b] = p.m_in[b * nc + j0];
+        m1[b] = p.m_in[b * nc + j1];
+    }
+    const double m = quad_sum(m0[0] + m1[0]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double mx = quad_sum(__builtin_fma(m0, x0[k], m1 * x1[k]));
+        const double mx = quad_sum(__builtin_fma(m0[0], x0[k], m1[0] * x1[k]));
         const double gx = quad_sum(x0[k] + x1[k]);
         c[k] = m > 0.0 ? mx / m : gx * 0.125;  // plain mean of the centres if massless
     }
 
-    double acc[20], mm[20], mono[20];
+    double acc[20], mono[20];
 #pragma unroll
     for (int b = 0; b < 20; ++b) acc[b] = 0.0;
-    mm[0] = m0;
-#pragma unroll
-    for (int b = 1; b < 20; ++b) mm[b] = p.m_in[b * nc + j0];
     monomials(x0[0] - c[0], x0[1] - c[1], x0[2] - c[2], mono);
-    moment_shift(acc, mm, mono, std::make_integer_sequence<int, 20>{});
-    mm[0] = m1;
-#pragma unroll
-    for (int b = 1; b < 20; ++b) mm[b] = p.m_in[b * nc + j1];
+    moment_shift(acc, m0, mono, std::make_integer_sequence<int, 20>{});
     monomials(x1[0] - c[0], x1[1] - c[1], x1[2] - c[2], mono);
-    moment_shift(acc, mm, mono, std::make_integer_sequence<int, 20>{});
+    moment_shift(acc, m1, mono, std::make_integer_sequence<int, 20>{});
 #pragma unroll
     for (int b = 0; b < 20; ++b) acc[b] = quad_sum(acc[b]);
 

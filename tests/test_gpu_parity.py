@@ -57,7 +57,8 @@ def test_multipole_single_block(ot):
     print("multipole worst", assert_parity(_host(L), ref, TOL, what="multipole"))
 
 
-@pytest.mark.parametrize("sched", [1, 2, 3])
+# 1 W8, 2 W16, 3 W8P2; 0x10 = persistent launch
+@pytest.mark.parametrize("sched", [1, 2, 3, 0x11, 0x12, 0x13])
 def test_batched_small_periodic_with_missing(ot, sched):
     batch, M, X = synthetic.batched_config(2, 21, missing_frac=0.5)
     ref = oracle.batched_forward(batch, M, X)
@@ -127,7 +128,7 @@ def _small_adjoint_case():
 
 
 # (target-role schedule, source-role schedule)
-@pytest.mark.parametrize("sched", [(1, 1), (2, 1), (3, 3), (2, 3)])
+@pytest.mark.parametrize("sched", [(1, 1), (2, 1), (3, 3), (2, 3), (0x12, 0x11), (0x11, 0x13)])
 def test_backward_small_open(ot, sched):
     batch, M, X = _small_adjoint_case()
     w = synthetic.weights(batch["T"], 42)
@@ -194,21 +195,25 @@ def test_autograd_function_matches_oracle(ot):
     assert L.dtype == torch.float64
 
 
-def test_step_graph_replays_match_eager(ot):
+@pytest.mark.parametrize("persistent", [False, True])
+def test_step_graph_replays_match_eager(ot, persistent):
     """The captured forward+adjoint graph, replayed several times with eager
     work and synchronisations in between, reproduces the eager results
-    bitwise on every replay."""
+    bitwise on every replay (persistent launches: the work counters are
+    zeroed by a kernel node of the graph on every replay)."""
     import torch
+    P = 0x10 if persistent else 0
+    fs, bs = 2 | P, ot.sched_bwd(2 | P, 1 | P)
     batch, M, X = synthetic.batched_config(3, 71, missing_frac=0.3)
     plan = ot.Plan.from_batch(batch)
     Md, Xd = _dev(M), _dev(X)
     wd = _dev(synthetic.weights(batch["T"], 72))
     NS, NT = batch["S"] * 512, batch["T"] * 512
     L0, gM0, gX0 = _empty(20, NT), _empty(20, NS), _empty(3, NS)
-    plan.multipole_batched(Md, Xd, L0)
-    plan.multipole_backward(Md, Xd, wd, gM0, gX0)
+    plan.multipole_batched(Md, Xd, L0, sched=fs & 0xF)
+    plan.multipole_backward(Md, Xd, wd, gM0, gX0, sched=ot.sched_bwd(2, 1))
     L, gM, gX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
-    plan.step_graph_create(Md, Xd, L, wd, gM, gX)
+    plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
     for rep in range(3):
         L.fill_(float("nan"))
         gX.fill_(float("nan"))
@@ -226,7 +231,8 @@ def test_autotune_choices_are_valid_and_exact(ot):
     Md, Xd = _dev(M), _dev(X)
     L = _empty(20, batch["T"] * 512)
     f, b = plan.autotune(Md, Xd, L)
-    assert f in (1, 2, 3) and (b & 0xff) in (1, 2, 3) and (b >> 8) in (1, 3)
+    assert (f & 0xF) in (1, 2, 3) and (b & 0xF) in (1, 2, 3) and ((b >> 8) & 0xF) in (1, 3)
+    assert not (f & ~0x1F) and not (b & ~0x1F1F)  # a shape, at most the persistent flag
     plan.multipole_batched(Md, Xd, L)   # AUTO -> tuned
     ref = oracle.batched_forward(batch, M, X, tsel=[0, 5, 26])
     got = _host(L).reshape(20, 27, 512)[:, [0, 5, 26]].reshape(20, -1)
@@ -237,10 +243,11 @@ def test_invalid_schedule_rejected(ot):
     batch, M, X = synthetic.batched_config(2, 91)
     plan = ot.Plan.from_batch(batch)
     L = _empty(20, batch["T"] * 512)
-    with pytest.raises(ot.OtFmmError):
-        plan.multipole_batched(_dev(M), _dev(X), L, sched=7)
+    for bad in (7, 0x10, 0x14, 0x20 | 2):
+        with pytest.raises(ot.OtFmmError):
+            plan.multipole_batched(_dev(M), _dev(X), L, sched=bad)
     gM, gX = _empty(20, batch["S"] * 512), _empty(3, batch["S"] * 512)
-    for bad in (ot.sched_bwd(2, 2), ot.sched_bwd(4, 1), 1 << 16):  # no 16-wavefront source role
+    for bad in (ot.sched_bwd(2, 2), ot.sched_bwd(4, 1), 1 << 16, ot.sched_bwd(2, 0x12), 0x10, 0x14):
         with pytest.raises(ot.OtFmmError):
             plan.multipole_backward(_dev(M), _dev(X), L, gM, gX, sched=bad)
 
@@ -261,7 +268,7 @@ def _cols(a, sel):
     return a.reshape(a.shape[0], -1, 512)[:, sel].reshape(a.shape[0], -1)
 
 
-@pytest.mark.parametrize("sched", [1, 2, 3])
+@pytest.mark.parametrize("sched", [1, 2, 3, 0x12])
 def test_config3_forward_sampled(ot, sched):
     """16^3 sub-grids, periodic, 15% missing 1-9 neighbours: every output of
     the launch is produced, a seeded sample of targets (half of them with
