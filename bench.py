@@ -57,10 +57,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel, sched, n):
-    """HBM-side bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain
-    copy of known size) from the committed counter summary, when it was taken
-    on this kernel source and this workload; else None."""
+def measured_counters(kernel, sched, n):
+    """Counter record of this kernel and schedule from the committed rocprofv3
+    summary (HBM-side bytes per launch: FETCH_SIZE + WRITE_SIZE scaled by a
+    plain copy of known size; issued FP64 operations per launch from the F64
+    instruction counters), when it was taken on these interaction sources and
+    this workload; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_32768_subgrids.json")
     if n != 32 or not os.path.exists(path):
@@ -76,8 +78,7 @@ def measured_traffic(kernel, sched, n):
     elif kernel == "adjoint_target":
         sched = sched & 0xff
     key = kernel + {1: "_w8", 2: "_w16", 3: "_w8p2"}[sched & 0xF] + ("_persistent" if sched & 0x10 else "")
-    k = rec["kernels"].get(key)
-    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
+    return rec["kernels"].get(key)
 
 
 def main():
@@ -170,7 +171,10 @@ def main():
         log("kernel %-15s %.3f ms  %.2f TFLOP/s" % (k, mean, kernels[k]["tflops"]))
     dom = max(kernels, key=lambda k: kernels[k]["mean_ms"])
     achieved = kernels[dom]["tflops"]
-    traffic = measured_traffic(dom, fs if dom == "forward" else bs, args.n)
+    counters = measured_counters(dom, fs if dom == "forward" else bs, args.n)
+    traffic = None if counters is None else counters["fetch_bytes"] + counters["write_bytes"]
+    issued = None if counters is None else round(
+        counters["issued_fp64_flop"] / (kernels[dom]["mean_ms"] * 1e-3) / 1e12, 3)
     fwd_pairs_s = pairs / (kernels["forward"]["mean_ms"] * 1e-3)
     sum_ms = sum(v["mean_ms"] for v in kernels.values())
     fwdbwd_flops = pairs * sum(FLOP_PER_PAIR.values()) / (ms_per_step * 1e-3) / 1e12
@@ -228,6 +232,9 @@ def main():
             "traffic_unit": "bytes per launch (HBM side, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_basis": "algorithmic FP64 ops per cell pair of the plain formulas (FMA = 2, "
                           "rsqrt = 1) x exact pairs per launch",
+            "issued_fp64_tflops": issued,
+            "issued_basis": "FP64 operations per launch counted by rocprofv3 (64 x (2 FMA + MUL + ADD "
+                            "+ TRANS) instruction counters, committed summary) / the live mean duration",
         },
         "kernels": kernels,
         "fwd_bwd_tflops": round(fwdbwd_flops, 3),
