@@ -124,6 +124,22 @@ int ot_fmm_plan_destroy(ot_fmm_plan plan);
  * counted from the descriptor (the unit of the throughput metric). */
 int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs);
 
+/* Host-only (no device call): validates a descriptor exactly as
+ * ot_fmm_plan_create does and returns its pair count; optionally the exact
+ * pairs of each target (work[T]) and the launch order of the targets
+ * (order[T]: longest work first, ties in target order). */
+int ot_fmm_count_pairs(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
+                       const double* period, int64_t* pairs, int64_t* work, int32_t* order);
+
+/* Host-only: the stencil tables the kernels use. slot_pairs[27] = pairs
+ * between the 8^3 targets and the neighbour block in each slot;
+ * offsets_per_target[2] = sources of one target of z parity 0 / 1;
+ * rows_per_parity[2] = entries (dz, dy, x-interval) of the per-parity row
+ * table the wavefronts walk.
+ * EUNSUPPORTED if the mirrored row table does not reproduce the stencil of
+ * every parity (the kernels then refuse to run). */
+int ot_fmm_stencil_info(int64_t* slot_pairs, int32_t* offsets_per_target, int32_t* rows_per_parity);
+
 /* Batched multipole forward: M[20][S*512], com[3][S*512] -> L[20][T*512]. */
 int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
                              int sched, void* stream);

@@ -93,6 +93,10 @@ _lib.ot_fmm_l2l.restype = _I
 _lib.ot_fmm_evaluate.argtypes = [ctypes.c_int64, _P, _P, _P, _P, _P]
 _lib.ot_fmm_evaluate.restype = _I
 
+_lib.ot_fmm_count_pairs.argtypes = [_I32, _I32, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P, _P]
+_lib.ot_fmm_count_pairs.restype = _I
+_lib.ot_fmm_stencil_info.argtypes = [_P, _P, _P]
+_lib.ot_fmm_stencil_info.restype = _I
 _CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p)
 _lib.ot_fmm_executor_create.argtypes = [_I, _I, ctypes.POINTER(_P)]
 _lib.ot_fmm_executor_destroy.argtypes = [_P]
@@ -175,24 +179,34 @@ def ot_fmm_multipole(M, com, L, stream=None):
 # ---------------------------------------------------------------------------
 # batched forms
 # ---------------------------------------------------------------------------
+def _descriptor_arrays(batch):
+    """Contiguous, typed and shape-checked (tgt, nbr, shift, period) of a descriptor."""
+    T = int(batch["T"])
+    tgt = np.ascontiguousarray(batch["tgt"], dtype=np.int32)
+    nbr = np.ascontiguousarray(batch["nbr"], dtype=np.int32)
+    if tgt.shape != (T,) or nbr.shape != (T, 27):
+        raise ValueError("tgt must be (T,) and nbr (T, 27)")
+    shift = batch.get("shift")
+    period = batch.get("period")
+    if shift is not None:
+        shift = np.ascontiguousarray(shift, dtype=np.int8)
+        if shift.shape != (T, 27, 3):
+            raise ValueError("shift must be (T, 27, 3)")
+    if period is not None:
+        period = np.ascontiguousarray(period, dtype=np.float64)
+        if period.shape != (3,):
+            raise ValueError("period must be (3,)")
+    return tgt, nbr, shift, period
+
+
 class Plan:
     """Validated batched descriptor with device tables (ot_fmm_plan)."""
 
     def __init__(self, S, T, tgt, nbr, shift=None, period=None):
         self.S = int(S)
         self.T = int(T)
-        tgt = np.ascontiguousarray(tgt, dtype=np.int32)
-        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
-        if tgt.shape != (self.T,) or nbr.shape != (self.T, 27):
-            raise ValueError("tgt must be (T,) and nbr (T, 27)")
-        if shift is not None:
-            shift = np.ascontiguousarray(shift, dtype=np.int8)
-            if shift.shape != (self.T, 27, 3):
-                raise ValueError("shift must be (T, 27, 3)")
-        if period is not None:
-            period = np.ascontiguousarray(period, dtype=np.float64)
-            if period.shape != (3,):
-                raise ValueError("period must be (3,)")
+        tgt, nbr, shift, period = _descriptor_arrays(
+            {"S": S, "T": T, "tgt": tgt, "nbr": nbr, "shift": shift, "period": period})
         h = ctypes.c_void_p()
         self._h = None
         _check(_lib.ot_fmm_plan_create(
@@ -501,3 +515,32 @@ class Executor:
         f = ctypes.c_void_p()
         _check(_lib.ot_fmm_future_create(self._h, ctypes.byref(f)), "ot_fmm_future_create")
         return Future(f, self)
+
+
+# ---------------------------------------------------------------------------
+# host-only descriptor and stencil queries (no device needed)
+# ---------------------------------------------------------------------------
+def ot_fmm_count_pairs(batch):
+    """(pairs, work per target, launch order) of a batched descriptor, validated
+    as ot_fmm_plan_create validates it."""
+    tgt, nbr, shift, period = _descriptor_arrays(batch)
+    T = int(batch["T"])
+    pairs = ctypes.c_int64()
+    work = np.zeros(T, np.int64)
+    order = np.zeros(T, np.int32)
+    _check(_lib.ot_fmm_count_pairs(int(batch["S"]), T, tgt.ctypes.data_as(_P), nbr.ctypes.data_as(_P),
+                                   None if shift is None else shift.ctypes.data_as(_P),
+                                   None if period is None else period.ctypes.data_as(_P),
+                                   ctypes.byref(pairs), work.ctypes.data_as(_P),
+                                   order.ctypes.data_as(_P)), "ot_fmm_count_pairs")
+    return pairs.value, work, order
+
+
+def ot_fmm_stencil_info():
+    """(pairs per neighbour slot [27], offsets per target [2], row-table entries [2])."""
+    sp = np.zeros(27, np.int64)
+    off = np.zeros(2, np.int32)
+    rows = np.zeros(2, np.int32)
+    _check(_lib.ot_fmm_stencil_info(sp.ctypes.data_as(_P), off.ctypes.data_as(_P), rows.ctypes.data_as(_P)),
+           "ot_fmm_stencil_info")
+    return sp, off, rows

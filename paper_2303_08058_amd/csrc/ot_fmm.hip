@@ -1166,6 +1166,83 @@ std::vector<int> lpt_order(const std::vector<int64_t>& work)
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+
+// Host part of a plan: validation of the descriptor, forward and inverse
+// relations, exact pair counts and the work orders (no device call).
+struct HostTables {
+    std::vector<int4> fwd, rev;
+    std::vector<int64_t> fwd_work;
+    std::vector<int> tg, fo, ro;
+    int64_t pairs = 0;
+};
+
+int build_host_tables(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
+                      const double* period, HostTables* h)
+{
+    if (S <= 0 || T <= 0) return fail(OT_FMM_EINVAL, "S and T must be positive");
+    if ((int64_t)S * kSub3 * 20 > ((int64_t)1 << 40) || (int64_t)T * 27 > ((int64_t)1 << 31))
+        return fail(OT_FMM_EINVAL, "descriptor too large");
+    if (!tgt || !nbr) return fail(OT_FMM_EINVAL, "null tgt or nbr");
+    if (shift && !period) return fail(OT_FMM_EINVAL, "shift given without period");
+    std::vector<char> seen(S, 0);
+    for (int t = 0; t < T; ++t) {
+        if (tgt[t] < 0 || tgt[t] >= S) return fail(OT_FMM_EINVAL, "tgt out of range");
+        if (seen[tgt[t]]) return fail(OT_FMM_EINVAL, "tgt entries must be distinct");
+        seen[tgt[t]] = 1;
+        for (int s = 0; s < 27; ++s) {
+            const int32_t v = nbr[(int64_t)t * 27 + s];
+            if (v < -1 || v >= S) return fail(OT_FMM_EINVAL, "nbr out of range");
+        }
+        if (nbr[(int64_t)t * 27 + 13] != tgt[t]) return fail(OT_FMM_EINVAL, "nbr[t][13] != tgt[t]");
+    }
+    if (period)
+        for (int k = 0; k < 3; ++k)
+            if (!(period[k] == period[k]) || period[k] > 1e15 || period[k] < -1e15)
+                return fail(OT_FMM_EINVAL, "period must be finite");
+    const SlotCounts& sc = slot_counts();
+    std::vector<int4>& fwd = h->fwd;
+    std::vector<int4>& rev = h->rev;
+    fwd.assign((size_t)T * 27, make_int4(0, 0, 0, 0));
+    rev.assign((size_t)S * 27, make_int4(0, 0, 0, 0));
+    for (auto& r : rev) r = make_int4(-1, -1, 0, 0);
+    std::vector<int64_t> fwd_work(T, 0), rev_work(S, 0);
+    int64_t pairs = 0;
+    for (int t = 0; t < T; ++t)
+        for (int s = 0; s < 27; ++s) {
+            const int32_t b = nbr[(int64_t)t * 27 + s];
+            int packed = 0, packed_neg = 0;
+            if (shift) {
+                for (int k = 0; k < 3; ++k) {
+                    const int v = shift[((int64_t)t * 27 + s) * 3 + k];
+                    packed |= (v & 0xff) << (8 * k);
+                    packed_neg |= ((-v) & 0xff) << (8 * k);
+                }
+            }
+            fwd[(size_t)t * 27 + s] = make_int4(b, b, packed, 0);
+            if (b < 0) continue;
+            if (shift)
+                for (int k = 0; k < 3; ++k)
+                    if (shift[((int64_t)t * 27 + s) * 3 + k] == -128)
+                        return fail(OT_FMM_EINVAL, "shift of -128 cannot be negated");
+            const size_t ri = (size_t)b * 27 + (26 - s);
+            if (rev[ri].x >= 0)
+                return fail(OT_FMM_EINVAL, "two targets claim the same (source, slot) relation");
+            rev[ri] = make_int4(t, tgt[t], packed_neg, 0);
+            fwd_work[t] += sc.pairs[s];
+            rev_work[b] += sc.pairs[s];
+            pairs += sc.pairs[s];
+        }
+    h->tg.assign(tgt, tgt + T);
+    h->fo = lpt_order(fwd_work);
+    h->ro = lpt_order(rev_work);
+    h->pairs = pairs;
+    h->fwd_work.swap(fwd_work);
+    return OT_FMM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ot_fmm_version(void) { return OT_FMM_VERSION; }
@@ -1219,59 +1296,16 @@ int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
     g_last_error.clear();
     if (!out) return fail(OT_FMM_EINVAL, "null output pointer");
     *out = nullptr;
-    if (S <= 0 || T <= 0) return fail(OT_FMM_EINVAL, "S and T must be positive");
-    if ((int64_t)S * kSub3 * 20 > ((int64_t)1 << 40) || (int64_t)T * 27 > ((int64_t)1 << 31))
-        return fail(OT_FMM_EINVAL, "descriptor too large");
-    if (!tgt || !nbr) return fail(OT_FMM_EINVAL, "null tgt or nbr");
-    if (shift && !period) return fail(OT_FMM_EINVAL, "shift given without period");
-    std::vector<char> seen(S, 0);
-    for (int t = 0; t < T; ++t) {
-        if (tgt[t] < 0 || tgt[t] >= S) return fail(OT_FMM_EINVAL, "tgt out of range");
-        if (seen[tgt[t]]) return fail(OT_FMM_EINVAL, "tgt entries must be distinct");
-        seen[tgt[t]] = 1;
-        for (int s = 0; s < 27; ++s) {
-            const int32_t v = nbr[(int64_t)t * 27 + s];
-            if (v < -1 || v >= S) return fail(OT_FMM_EINVAL, "nbr out of range");
-        }
-        if (nbr[(int64_t)t * 27 + 13] != tgt[t]) return fail(OT_FMM_EINVAL, "nbr[t][13] != tgt[t]");
-    }
-    if (period)
-        for (int k = 0; k < 3; ++k)
-            if (!(period[k] == period[k]) || period[k] > 1e15 || period[k] < -1e15)
-                return fail(OT_FMM_EINVAL, "period must be finite");
-    const SlotCounts& sc = slot_counts();
-    std::vector<int4> fwd((size_t)T * 27), rev((size_t)S * 27);
-    for (auto& r : rev) r = make_int4(-1, -1, 0, 0);
-    std::vector<int64_t> fwd_work(T, 0), rev_work(S, 0);
-    int64_t pairs = 0;
-    for (int t = 0; t < T; ++t)
-        for (int s = 0; s < 27; ++s) {
-            const int32_t b = nbr[(int64_t)t * 27 + s];
-            int packed = 0, packed_neg = 0;
-            if (shift) {
-                for (int k = 0; k < 3; ++k) {
-                    const int v = shift[((int64_t)t * 27 + s) * 3 + k];
-                    packed |= (v & 0xff) << (8 * k);
-                    packed_neg |= ((-v) & 0xff) << (8 * k);
-                }
-            }
-            fwd[(size_t)t * 27 + s] = make_int4(b, b, packed, 0);
-            if (b < 0) continue;
-            if (shift)
-                for (int k = 0; k < 3; ++k)
-                    if (shift[((int64_t)t * 27 + s) * 3 + k] == -128)
-                        return fail(OT_FMM_EINVAL, "shift of -128 cannot be negated");
-            const size_t ri = (size_t)b * 27 + (26 - s);
-            if (rev[ri].x >= 0)
-                return fail(OT_FMM_EINVAL, "two targets claim the same (source, slot) relation");
-            rev[ri] = make_int4(t, tgt[t], packed_neg, 0);
-            fwd_work[t] += sc.pairs[s];
-            rev_work[b] += sc.pairs[s];
-            pairs += sc.pairs[s];
-        }
-    std::vector<int> tg(tgt, tgt + T);
-    std::vector<int> fo = lpt_order(fwd_work), ro = lpt_order(rev_work);
-    int rc = ensure_device();
+    HostTables ht;
+    int rc = build_host_tables(S, T, tgt, nbr, shift, period, &ht);
+    if (rc) return rc;
+    const std::vector<int4>& fwd = ht.fwd;
+    const std::vector<int4>& rev = ht.rev;
+    const std::vector<int>& tg = ht.tg;
+    const std::vector<int>& fo = ht.fo;
+    const std::vector<int>& ro = ht.ro;
+    const int64_t pairs = ht.pairs;
+    rc = ensure_device();
     if (rc) return rc;
 
     ot_fmm_plan p = new (std::nothrow) ot_fmm_plan_s();
@@ -1311,6 +1345,34 @@ int ot_fmm_plan_destroy(ot_fmm_plan plan)
     if (!plan) return OT_FMM_OK;
     free_plan_memory(plan);
     delete plan;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_count_pairs(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
+                       const double* period, int64_t* pairs, int64_t* work, int32_t* order)
+{
+    g_last_error.clear();
+    if (!pairs) return fail(OT_FMM_EINVAL, "null pairs pointer");
+    HostTables ht;
+    int rc = build_host_tables(S, T, tgt, nbr, shift, period, &ht);
+    if (rc) return rc;
+    *pairs = ht.pairs;
+    if (work) std::copy(ht.fwd_work.begin(), ht.fwd_work.end(), work);
+    if (order) std::copy(ht.fo.begin(), ht.fo.end(), order);
+    return OT_FMM_OK;
+}
+
+int ot_fmm_stencil_info(int64_t* slot_pairs, int32_t* offsets_per_target, int32_t* rows_per_parity)
+{
+    g_last_error.clear();
+    if (!slot_pairs || !offsets_per_target || !rows_per_parity) return fail(OT_FMM_EINVAL, "null argument");
+    const SlotCounts& sc = slot_counts();
+    for (int s = 0; s < 27; ++s) slot_pairs[s] = sc.pairs[s];
+    for (int pz = 0; pz < 2; ++pz) {
+        offsets_per_target[pz] = kStencilHost.count[pz];
+        rows_per_parity[pz] = kStencilHost.range[pz][2 * kReach][2];
+    }
+    if (!sc.mirror_ok) return fail(OT_FMM_EUNSUPPORTED, "stencil mirror check failed");
     return OT_FMM_OK;
 }
 
