@@ -50,7 +50,7 @@ def sched_name(s):
     return base + ("+persistent" if s & 0x10 else "")
 
 # sources of the interaction kernels (the counter record names their hash)
-INTERACTION_SOURCES = ("ot_common.h", "ot_fmm.hip")
+INTERACTION_SOURCES = ("ot_common.h", "ot_interact.h")
 
 
 def log(*a):
