@@ -47,7 +47,7 @@ FLOP_PER_PAIR = {
 def sched_name(s):
     """Name of a one-pass schedule code (shape, optionally + persistent)."""
     base = {1: "W8", 2: "W16", 3: "W8P2"}[s & 0xF]
-    return base + ("+persistent" if s & 0x10 else "")
+    return base + ("+persistent" if s & 0x10 else "") + ("+xcd-local" if s & 0x20 else "")
 
 # sources of the interaction kernels (the counter record names their hash)
 INTERACTION_SOURCES = ("ot_common.h", "ot_interact.h")
@@ -77,7 +77,8 @@ def measured_counters(kernel, sched, n):
         sched = sched >> 8
     elif kernel == "adjoint_target":
         sched = sched & 0xff
-    key = kernel + {1: "_w8", 2: "_w16", 3: "_w8p2"}[sched & 0xF] + ("_persistent" if sched & 0x10 else "")
+    key = (kernel + {1: "_w8", 2: "_w16", 3: "_w8p2"}[sched & 0xF] + ("_persistent" if sched & 0x10 else "")
+           + ("_local" if sched & 0x20 else ""))
     return rec["kernels"].get(key)
 
 
@@ -93,6 +94,10 @@ def main():
                     help="approximate CPU time of the oracle baseline (0: skip)")
     ap.add_argument("--tree-steps", type=int, default=10,
                     help="timed launches of each tree pass (0: skip)")
+    ap.add_argument("--fwd-sched", type=lambda v: int(v, 0), default=None,
+                    help="forward schedule code (skips the autotuner; e.g. 0x22 = W16 + XCD-local order)")
+    ap.add_argument("--bwd-sched", type=lambda v: int(v, 0), default=None,
+                    help="backward schedule code, target role | source role << 8 (with --fwd-sched)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counters)")
     args = ap.parse_args()
@@ -130,7 +135,10 @@ def main():
     torch.cuda.synchronize()
     log("plan: %d targets, %d pairs" % (batch["T"], pairs))
 
-    fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
+    if args.fwd_sched is not None and args.bwd_sched is not None:
+        fs, bs = args.fwd_sched, args.bwd_sched
+    else:
+        fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
     log("autotuned schedules: forward %s, adjoint target role %s, source role %s"
         % (sched_name(fs), sched_name(bs & 0xff), sched_name(bs >> 8)))
     plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)

@@ -74,7 +74,14 @@ enum {
      * are resident at once, taking work-list entries (longest first) from a
      * counter that a one-thread kernel zeroes just before; up to 64 such
      * launches of one plan may be in flight at once */
-    OT_FMM_SCHED_PERSISTENT = 0x10
+    OT_FMM_SCHED_PERSISTENT = 0x10,
+    /* flag, OR-ed into a schedule: XCD-aware work order -- entries sorted
+     * along a Morton curve of the lattice positions recovered from the
+     * neighbour table, cut into one piece of equal work per XCD and
+     * interleaved, so that the work-groups each XCD runs at once are spatial
+     * neighbours sharing their staged blocks in that XCD's L2 (instead of
+     * longest work first) */
+    OT_FMM_SCHED_LOCAL = 0x20
 };
 #define OT_FMM_SCHED_BWD(target_role, source_role) ((target_role) | ((source_role) << 8))
 
@@ -130,6 +137,14 @@ int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs);
  * (order[T]: longest work first, ties in target order). */
 int ot_fmm_count_pairs(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
                        const double* period, int64_t* pairs, int64_t* work, int32_t* order);
+
+/* Host-only: the other work orders of a plan built from this descriptor, for
+ * a device with `nxcd` XCDs: fwd_local[T] (targets, XCD-aware),
+ * rev_lpt[S] and rev_local[S] (store sub-grids of the adjoint's source-role
+ * pass, longest work first / XCD-aware). Any output may be NULL. */
+int ot_fmm_work_orders(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
+                       const double* period, int32_t nxcd, int32_t* fwd_local, int32_t* rev_lpt,
+                       int32_t* rev_local);
 
 /* Host-only: the stencil tables the kernels use. slot_pairs[27] = pairs
  * between the 8^3 targets and the neighbour block in each slot;

@@ -36,6 +36,7 @@ SCHED_W8 = 1
 SCHED_W16 = 2
 SCHED_W8P2 = 3
 SCHED_PERSISTENT = 0x10  # flag OR-ed into a schedule
+SCHED_LOCAL = 0x20       # flag OR-ed into a schedule: XCD-aware work order
 
 
 def sched_bwd(target_role=SCHED_AUTO, source_role=SCHED_AUTO):
@@ -95,6 +96,8 @@ _lib.ot_fmm_evaluate.restype = _I
 
 _lib.ot_fmm_count_pairs.argtypes = [_I32, _I32, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64), _P, _P]
 _lib.ot_fmm_count_pairs.restype = _I
+_lib.ot_fmm_work_orders.argtypes = [_I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P]
+_lib.ot_fmm_work_orders.restype = _I
 _lib.ot_fmm_stencil_info.argtypes = [_P, _P, _P]
 _lib.ot_fmm_stencil_info.restype = _I
 _CB = ctypes.CFUNCTYPE(None, ctypes.c_void_p)
@@ -544,3 +547,18 @@ def ot_fmm_stencil_info():
     _check(_lib.ot_fmm_stencil_info(sp.ctypes.data_as(_P), off.ctypes.data_as(_P), rows.ctypes.data_as(_P)),
            "ot_fmm_stencil_info")
     return sp, off, rows
+
+
+def ot_fmm_work_orders(batch, nxcd=8):
+    """(targets XCD-aware, store sub-grids longest-first, store sub-grids XCD-aware)."""
+    tgt, nbr, shift, period = _descriptor_arrays(batch)
+    S, T = int(batch["S"]), int(batch["T"])
+    fl = np.zeros(T, np.int32)
+    rl = np.zeros(S, np.int32)
+    rloc = np.zeros(S, np.int32)
+    _check(_lib.ot_fmm_work_orders(S, T, tgt.ctypes.data_as(_P), nbr.ctypes.data_as(_P),
+                                   None if shift is None else shift.ctypes.data_as(_P),
+                                   None if period is None else period.ctypes.data_as(_P), int(nxcd),
+                                   fl.ctypes.data_as(_P), rl.ctypes.data_as(_P), rloc.ctypes.data_as(_P)),
+           "ot_fmm_work_orders")
+    return fl, rl, rloc

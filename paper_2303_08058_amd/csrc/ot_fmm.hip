@@ -105,13 +105,17 @@ int launch(const KParams& kp, int nblocks, hipStream_t stream)
 
 constexpr int kDefaultSourceSched = OT_FMM_SCHED_W8;
 
-// a shape (W8, W16, W8P2), optionally with the persistent flag; or AUTO alone
+constexpr int kShapeMask = 0x0f;
+
+// a shape (W8, W16, W8P2), optionally with the persistent and local-order
+// flags; or AUTO alone
 bool valid_fwd_sched(int s)
 {
     if (s == OT_FMM_SCHED_AUTO) return true;
-    const int shape = s & ~OT_FMM_SCHED_PERSISTENT;
-    return s > 0 && s <= (OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT) && shape >= OT_FMM_SCHED_W8 &&
-           shape <= OT_FMM_SCHED_W8P2;
+    const int shape = s & kShapeMask;
+    const int flags = s & ~kShapeMask;
+    return s > 0 && (flags & ~(OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL)) == 0 &&
+           shape >= OT_FMM_SCHED_W8 && shape <= OT_FMM_SCHED_W8P2;
 }
 
 // target role: any forward schedule; source role: AUTO, W8 or W8P2 (either
@@ -120,8 +124,7 @@ bool valid_bwd_sched(int s)
 {
     if (s < 0 || (s >> 16) != 0) return false;
     const int t = s & 0xff, r = s >> 8;
-    const int rshape = r & ~OT_FMM_SCHED_PERSISTENT;
-    return valid_fwd_sched(t) && valid_fwd_sched(r) && rshape != OT_FMM_SCHED_W16;
+    return valid_fwd_sched(t) && valid_fwd_sched(r) && (r & kShapeMask) != OT_FMM_SCHED_W16;
 }
 
 constexpr int kCounterSlots = 64;
@@ -143,8 +146,10 @@ struct ot_fmm_plan_s {
     int4* d_fwd_rel = nullptr;  // [T][27]
     int4* d_rev_rel = nullptr;  // [S][27]
     int* d_tgt = nullptr;       // [T]
-    int* d_fwd_order = nullptr; // [T]
+    int* d_fwd_order = nullptr; // [T] longest work first
     int* d_rev_order = nullptr; // [S]
+    int* d_fwd_local = nullptr; // [T] XCD-aware (OT_FMM_SCHED_LOCAL)
+    int* d_rev_local = nullptr; // [S]
     int tuned_fwd = 0, tuned_bwd = 0;
     // persistent launches: one work counter per launch in flight (rotating)
     int* d_counters = nullptr;  // [kCounterSlots]
@@ -243,7 +248,8 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
     sched = pick_fwd(sched, plan->tuned_fwd);
     const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
-    const int shape = sched & ~OT_FMM_SCHED_PERSISTENT;
+    if (sched & OT_FMM_SCHED_LOCAL) kp.order = plan->d_fwd_local;
+    const int shape = sched & kShapeMask;
     if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FWD_STORE, 8>(plan, 0, kp, plan->T, pers, stream);
     if (shape == OT_FMM_SCHED_W16)
         return launch_timed<MODE_FWD_STORE, 16>(plan, 0, kp, plan->T, pers, stream);
@@ -282,7 +288,8 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     // the source-role pass has 8 wavefronts (its 40 accumulators do not fit
     // the register budget of 16): one pass, or two with split rows
     const bool spers = (ssched & OT_FMM_SCHED_PERSISTENT) != 0;
-    int rc = (ssched & ~OT_FMM_SCHED_PERSISTENT) == OT_FMM_SCHED_W8P2
+    if (ssched & OT_FMM_SCHED_LOCAL) b2.order = plan->d_rev_local;
+    int rc = (ssched & kShapeMask) == OT_FMM_SCHED_W8P2
                  ? launch_timed<MODE_B2_STORE, 8, 2>(plan, 1, b2, plan->S, spers, stream)
                  : launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, spers, stream);
     if (rc) return rc;
@@ -302,7 +309,8 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     b1.out_blk = plan->d_tgt;
     for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
     const bool tpers = (tsched & OT_FMM_SCHED_PERSISTENT) != 0;
-    const int tshape = tsched & ~OT_FMM_SCHED_PERSISTENT;
+    if (tsched & OT_FMM_SCHED_LOCAL) b1.order = plan->d_fwd_local;
+    const int tshape = tsched & kShapeMask;
     if (tshape == OT_FMM_SCHED_W16)
         return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, tpers, stream);
     if (tshape == OT_FMM_SCHED_W8P2)
@@ -336,6 +344,8 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_tgt);
     (void)hipFree(p->d_fwd_order);
     (void)hipFree(p->d_rev_order);
+    (void)hipFree(p->d_fwd_local);
+    (void)hipFree(p->d_rev_local);
     (void)hipFree(p->d_counters);
 }
 
@@ -347,6 +357,93 @@ std::vector<int> lpt_order(const std::vector<int64_t>& work)
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[a] > work[b]; });
     return idx;
+}
+
+// Spatial position of neighbour slot q relative to the owner.
+inline void slot_delta(int q, int* d)
+{
+    d[0] = q % 3 - 1;
+    d[1] = (q / 3) % 3 - 1;
+    d[2] = q / 9 - 1;
+}
+
+uint64_t spread_bits(uint64_t v)  // 21 bits -> every third bit
+{
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+}
+
+// XCD-aware work order. A launch's work-groups go to the XCDs round robin
+// (work-group b to XCD b % nxcd), and each XCD has its own L2. Lattice
+// coordinates are recovered from the neighbour graph (breadth-first, one
+// component at a time), the entries are sorted along a Morton curve, the curve
+// is cut into nxcd pieces of equal work, and the pieces are interleaved so
+// that each XCD walks one spatially compact piece: the neighbour blocks that
+// its concurrently resident work-groups stage overlap and are found in its L2.
+// adj[v] lists (neighbour entry, slot of the neighbour seen from v).
+std::vector<int> locality_order(const std::vector<std::vector<std::pair<int, int>>>& adj,
+                                const std::vector<int64_t>& work, int nxcd)
+{
+    const int n = (int)adj.size();
+    std::vector<int> comp(n, -1);
+    std::vector<std::array<int64_t, 3>> pos(n);
+    std::vector<int> queue;
+    queue.reserve(n);
+    int ncomp = 0;
+    for (int seed = 0; seed < n; ++seed) {
+        if (comp[seed] >= 0) continue;
+        const size_t first = queue.size();
+        comp[seed] = ncomp;
+        pos[seed] = {0, 0, 0};
+        queue.push_back(seed);
+        for (size_t h = first; h < queue.size(); ++h) {
+            const int v = queue[h];
+            for (const auto& e : adj[v]) {
+                if (comp[e.first] >= 0) continue;
+                int d[3];
+                slot_delta(e.second, d);
+                comp[e.first] = ncomp;
+                pos[e.first] = {pos[v][0] + d[0], pos[v][1] + d[1], pos[v][2] + d[2]};
+                queue.push_back(e.first);
+            }
+        }
+        int64_t lo[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+        for (size_t h = first; h < queue.size(); ++h)
+            for (int k = 0; k < 3; ++k) lo[k] = std::min(lo[k], pos[queue[h]][k]);
+        for (size_t h = first; h < queue.size(); ++h)
+            for (int k = 0; k < 3; ++k) pos[queue[h]][k] -= lo[k];
+        ++ncomp;
+    }
+    std::vector<uint64_t> key(n);
+    for (int v = 0; v < n; ++v)
+        key[v] = spread_bits((uint64_t)pos[v][0]) | spread_bits((uint64_t)pos[v][1]) << 1 |
+                 spread_bits((uint64_t)pos[v][2]) << 2;
+    std::vector<int> curve(n);
+    std::iota(curve.begin(), curve.end(), 0);
+    std::stable_sort(curve.begin(), curve.end(), [&](int a, int b) {
+        return comp[a] != comp[b] ? comp[a] < comp[b] : key[a] < key[b];
+    });
+    // pieces of equal work
+    int64_t total = 0;
+    for (int64_t w : work) total += w;
+    std::vector<std::vector<int>> piece(nxcd);
+    int64_t run = 0;
+    for (int v : curve) {
+        const int x = total > 0 ? (int)std::min<int64_t>(nxcd - 1, run * nxcd / total) : 0;
+        piece[x].push_back(v);
+        run += work[v];
+    }
+    std::vector<int> order;
+    order.reserve(n);
+    for (size_t i = 0; order.size() < (size_t)n; ++i)
+        for (int x = 0; x < nxcd; ++x)
+            if (i < piece[x].size()) order.push_back(piece[x][i]);
+    return order;
 }
 
 }  // namespace
@@ -362,8 +459,29 @@ struct HostTables {
     std::vector<int4> fwd, rev;
     std::vector<int64_t> fwd_work;
     std::vector<int> tg, fo, ro;
+    std::vector<int> fo_local, ro_local;  // XCD-aware orders (filled by make_local_orders)
+    std::vector<int64_t> rev_work;
     int64_t pairs = 0;
 };
+
+// XCD-aware orders of both work lists: targets linked through their
+// neighbour slots, store sub-grids through the targets that see them.
+void make_local_orders(int32_t S, int32_t T, const int32_t* nbr, HostTables* h, int nxcd)
+{
+    std::vector<int> tindex(S, -1);
+    for (int t = 0; t < T; ++t) tindex[h->tg[t]] = t;
+    std::vector<std::vector<std::pair<int, int>>> adj(T), radj(S);
+    for (int t = 0; t < T; ++t)
+        for (int q = 0; q < 27; ++q) {
+            const int32_t b = nbr[(int64_t)t * 27 + q];
+            if (q == 13 || b < 0) continue;
+            if (tindex[b] >= 0) adj[t].emplace_back(tindex[b], q);
+            // store block b sees the target's own block at the opposite slot
+            radj[b].emplace_back(h->tg[t], 26 - q);
+        }
+    h->fo_local = locality_order(adj, h->fwd_work, nxcd);
+    h->ro_local = locality_order(radj, h->rev_work, nxcd);
+}
 
 int build_host_tables(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
                       const double* period, HostTables* h)
@@ -426,6 +544,7 @@ int build_host_tables(int32_t S, int32_t T, const int32_t* tgt, const int32_t* n
     h->ro = lpt_order(rev_work);
     h->pairs = pairs;
     h->fwd_work.swap(fwd_work);
+    h->rev_work.swap(rev_work);
     return OT_FMM_OK;
 }
 
@@ -515,10 +634,15 @@ int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
         return hip_fail(e, "hipGetDeviceProperties");
     }
     p->n_cu = prop.multiProcessorCount;
+    int nxcd = 1;
+    if (hipDeviceGetAttribute(&nxcd, hipDeviceAttributeNumberOfXccs, p->device) != hipSuccess || nxcd < 1)
+        nxcd = 1;
+    make_local_orders(S, T, nbr, &ht, nxcd);
     const std::vector<int> zeros(kCounterSlots, 0);
     if ((rc = upload(&p->d_fwd_rel, fwd)) || (rc = upload(&p->d_rev_rel, rev)) ||
         (rc = upload(&p->d_tgt, tg)) || (rc = upload(&p->d_fwd_order, fo)) ||
-        (rc = upload(&p->d_rev_order, ro)) || (rc = upload(&p->d_counters, zeros))) {
+        (rc = upload(&p->d_rev_order, ro)) || (rc = upload(&p->d_counters, zeros)) ||
+        (rc = upload(&p->d_fwd_local, ht.fo_local)) || (rc = upload(&p->d_rev_local, ht.ro_local))) {
         free_plan_memory(p);
         delete p;
         return rc;
@@ -547,6 +671,22 @@ int ot_fmm_count_pairs(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
     *pairs = ht.pairs;
     if (work) std::copy(ht.fwd_work.begin(), ht.fwd_work.end(), work);
     if (order) std::copy(ht.fo.begin(), ht.fo.end(), order);
+    return OT_FMM_OK;
+}
+
+int ot_fmm_work_orders(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
+                       const double* period, int32_t nxcd, int32_t* fwd_local, int32_t* rev_lpt,
+                       int32_t* rev_local)
+{
+    g_last_error.clear();
+    if (nxcd < 1 || nxcd > 64) return fail(OT_FMM_EINVAL, "nxcd must be in [1, 64]");
+    HostTables ht;
+    int rc = build_host_tables(S, T, tgt, nbr, shift, period, &ht);
+    if (rc) return rc;
+    make_local_orders(S, T, nbr, &ht, nxcd);
+    if (fwd_local) std::copy(ht.fo_local.begin(), ht.fo_local.end(), fwd_local);
+    if (rev_lpt) std::copy(ht.ro.begin(), ht.ro.end(), rev_lpt);
+    if (rev_local) std::copy(ht.ro_local.begin(), ht.ro_local.end(), rev_local);
     return OT_FMM_OK;
 }
 
@@ -641,6 +781,7 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
     for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2})
         if ((rc = try_fwd(cand))) break;
     if (!rc) rc = try_fwd(best_f | OT_FMM_SCHED_PERSISTENT);
+    if (!rc) rc = try_fwd(best_f | OT_FMM_SCHED_LOCAL);
     int best_b = OT_FMM_SCHED_W16 | (kDefaultSourceSched << 8);
     if (!rc && with_bwd) {
         // source role first (target role W16), then the target role with it
@@ -657,10 +798,12 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
         for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
             if ((rc = try_bwd(OT_FMM_SCHED_W16 | (cand << 8)))) break;
         if (!rc) rc = try_bwd(best_b | (OT_FMM_SCHED_PERSISTENT << 8));
+        if (!rc) rc = try_bwd(best_b | (OT_FMM_SCHED_LOCAL << 8));
         const int src = best_b >> 8;
         for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
             if (!rc) rc = try_bwd(cand | (src << 8));
         if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_PERSISTENT);
+        if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_LOCAL);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

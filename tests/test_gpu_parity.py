@@ -58,7 +58,8 @@ def test_multipole_single_block(ot):
 
 
 # 1 W8, 2 W16, 3 W8P2; 0x10 = persistent launch
-@pytest.mark.parametrize("sched", [1, 2, 3, 0x11, 0x12, 0x13])
+# 0x20 = XCD-aware work order
+@pytest.mark.parametrize("sched", [1, 2, 3, 0x11, 0x12, 0x13, 0x22, 0x31])
 def test_batched_small_periodic_with_missing(ot, sched):
     batch, M, X = synthetic.batched_config(2, 21, missing_frac=0.5)
     ref = oracle.batched_forward(batch, M, X)
@@ -128,7 +129,8 @@ def _small_adjoint_case():
 
 
 # (target-role schedule, source-role schedule)
-@pytest.mark.parametrize("sched", [(1, 1), (2, 1), (3, 3), (2, 3), (0x12, 0x11), (0x11, 0x13)])
+@pytest.mark.parametrize("sched", [(1, 1), (2, 1), (3, 3), (2, 3), (0x12, 0x11), (0x11, 0x13), (0x22, 0x21),
+                                   (0x32, 0x31)])
 def test_backward_small_open(ot, sched):
     batch, M, X = _small_adjoint_case()
     w = synthetic.weights(batch["T"], 42)
@@ -232,7 +234,7 @@ def test_autotune_choices_are_valid_and_exact(ot):
     L = _empty(20, batch["T"] * 512)
     f, b = plan.autotune(Md, Xd, L)
     assert (f & 0xF) in (1, 2, 3) and (b & 0xF) in (1, 2, 3) and ((b >> 8) & 0xF) in (1, 3)
-    assert not (f & ~0x1F) and not (b & ~0x1F1F)  # a shape, at most the persistent flag
+    assert not (f & ~0x3F) and not (b & ~0x3F3F)  # a shape and the persistent / local-order flags
     plan.multipole_batched(Md, Xd, L)   # AUTO -> tuned
     ref = oracle.batched_forward(batch, M, X, tsel=[0, 5, 26])
     got = _host(L).reshape(20, 27, 512)[:, [0, 5, 26]].reshape(20, -1)
@@ -243,7 +245,7 @@ def test_invalid_schedule_rejected(ot):
     batch, M, X = synthetic.batched_config(2, 91)
     plan = ot.Plan.from_batch(batch)
     L = _empty(20, batch["T"] * 512)
-    for bad in (7, 0x10, 0x14, 0x20 | 2):
+    for bad in (7, 0x10, 0x14, 0x40 | 2, 0x20):
         with pytest.raises(ot.OtFmmError):
             plan.multipole_batched(_dev(M), _dev(X), L, sched=bad)
     gM, gX = _empty(20, batch["S"] * 512), _empty(3, batch["S"] * 512)
@@ -268,7 +270,7 @@ def _cols(a, sel):
     return a.reshape(a.shape[0], -1, 512)[:, sel].reshape(a.shape[0], -1)
 
 
-@pytest.mark.parametrize("sched", [1, 2, 3, 0x12])
+@pytest.mark.parametrize("sched", [1, 2, 3, 0x12, 0x22])
 def test_config3_forward_sampled(ot, sched):
     """16^3 sub-grids, periodic, 15% missing 1-9 neighbours: every output of
     the launch is produced, a seeded sample of targets (half of them with

@@ -103,3 +103,48 @@ def test_descriptor_validation():
     _bad(batch, nbr=nbr)
     # and a valid descriptor passes
     assert ot.ot_fmm_count_pairs(batch)[0] == 8 * 512 * 1799
+
+
+def _piece_locality(order, batch, nxcd):
+    """Fraction of the (item, neighbour item) relations whose two ends run on
+    the same XCD (work-group b on XCD b % nxcd)."""
+    xcd = np.empty(len(order), np.int64)
+    xcd[order] = np.arange(len(order)) % nxcd
+    tindex = -np.ones(batch["S"], np.int64)
+    tindex[batch["tgt"]] = np.arange(batch["T"])
+    same = total = 0
+    for t in range(batch["T"]):
+        for q in range(27):
+            b = batch["nbr"][t, q]
+            if q == 13 or b < 0 or tindex[b] < 0:
+                continue
+            total += 1
+            same += xcd[t] == xcd[tindex[b]]
+    return same / total
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_xcd_local_orders(periodic):
+    batch = synthetic.apply_missing(synthetic.lattice_batch(8, periodic=periodic), 0.2, synthetic._rng(5))
+    fl, rl, rloc = ot.ot_fmm_work_orders(batch, nxcd=8)
+    for o, n in ((fl, batch["T"]), (rl, batch["S"]), (rloc, batch["S"])):
+        assert np.array_equal(np.sort(o), np.arange(n))
+    # the longest-first store order of the source-role pass: non-increasing work
+    # (a store block's work = the pairs of the targets that see it)
+    sp = brute_slot_pairs()
+    rw = np.zeros(batch["S"], np.int64)
+    for t in range(batch["T"]):
+        for q in range(27):
+            b = batch["nbr"][t, q]
+            if b >= 0:
+                rw[b] += sp[q]
+    assert np.all(np.diff(rw[rl]) <= 0)
+    # pieces are spatially compact: many neighbour relations stay on one XCD,
+    # against ~1/8 for the longest-first order dealt round robin
+    _, _, lpt = ot.ot_fmm_count_pairs(batch)
+    loc, ref = _piece_locality(fl, batch, 8), _piece_locality(lpt, batch, 8)
+    assert loc > 0.45 and ref < 0.3, (loc, ref)  # a 4^3 piece keeps at most 56% of its 26-neighbour relations
+    # each XCD's piece carries about 1/8 of the work
+    _, work, _ = ot.ot_fmm_count_pairs(batch)
+    per = np.bincount(np.argsort(fl) % 8, weights=work, minlength=8)
+    assert per.max() / per.min() < 1.05
