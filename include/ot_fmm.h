@@ -30,6 +30,8 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). The
  *     compute calls only enqueue work; they never synchronize or allocate, and
  *     they may be captured into a hipGraph by the caller.
+ *   - Outputs must not overlap inputs or each other (checked from the array
+ *     extents: OT_FMM_EINVAL).
  *   - Return value: OT_FMM_OK or a negative error code. On OT_FMM_EINVAL
  *     nothing was enqueued. Details of the last error of the calling thread
  *     are available from ot_fmm_last_error(). Device faults surface at the

@@ -49,6 +49,7 @@
 #include <vector>
 
 #include "ot_common.h"
+#include "ot_host.h"
 #include "ot_fmm.h"
 #include "ot_interact.h"
 
@@ -574,6 +575,8 @@ int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stre
     g_last_error.clear();
     if (!aligned16(mass) || !aligned16(com) || !aligned16(L))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (overlap(L, 20 * kSub3, mass, kHalo3) || overlap(L, 20 * kSub3, com, 3 * kHalo3))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
     int rc = ensure_device();
     if (rc) return rc;
     KParams kp{};
@@ -588,6 +591,8 @@ int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream
     g_last_error.clear();
     if (!aligned16(M) || !aligned16(com) || !aligned16(L))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (overlap(L, 20 * kSub3, M, 20 * kHalo3) || overlap(L, 20 * kSub3, com, 3 * kHalo3))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
     int rc = ensure_device();
     if (rc) return rc;
     KParams kp{};
@@ -720,6 +725,9 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
     if (rc) return rc;
     if (!aligned16(M) || !aligned16(com) || !aligned16(L))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
     if (!valid_fwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
     return fwd_batched(plan, M, com, L, sched, (hipStream_t)stream);
 }
@@ -733,8 +741,15 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
     if (rc) return rc;
     if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(gM) || !aligned16(gcom))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
-    if (gM == M || gM == gL || gcom == com || (const double*)gcom == gL || (const double*)gM == com)
-        return fail(OT_FMM_EINVAL, "outputs alias inputs");
+    {
+        const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+        const double* in[3] = {M, com, gL};
+        const int64_t nin[3] = {20 * NS, 3 * NS, 20 * NT};
+        for (int i = 0; i < 3; ++i)
+            if (overlap(gM, 20 * NS, in[i], nin[i]) || overlap(gcom, 3 * NS, in[i], nin[i]))
+                return fail(OT_FMM_EINVAL, "outputs overlap inputs");
+        if (overlap(gM, 20 * NS, gcom, 3 * NS)) return fail(OT_FMM_EINVAL, "gM overlaps gcom");
+    }
     if (!valid_bwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown backward schedule");
     return bwd_batched(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
 }

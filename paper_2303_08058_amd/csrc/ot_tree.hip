@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "ot_common.h"
+#include "ot_host.h"
 #include "ot_fmm.h"
 
 using namespace otfmm;
@@ -336,6 +337,13 @@ int ot_fmm_m2m(ot_fmm_tree tree, const double* Mc, const double* comc, double* M
     if (rc) return rc;
     if (!aligned16(Mc) || !aligned16(comc) || !aligned16(Mp) || !aligned16(comp))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    {
+        const int64_t nc = (int64_t)tree->Sc * kSub3, np = (int64_t)tree->Sp * kSub3;
+        if (overlap(Mp, 20 * np, Mc, 20 * nc) || overlap(Mp, 20 * np, comc, 3 * nc) ||
+            overlap(comp, 3 * np, Mc, 20 * nc) || overlap(comp, 3 * np, comc, 3 * nc) ||
+            overlap(Mp, 20 * np, comp, 3 * np))
+            return fail(OT_FMM_EINVAL, "outputs overlap inputs or each other");
+    }
     TreeParams tp{};
     tp.children = tree->d_children;
     tp.m_in = Mc;
@@ -359,6 +367,12 @@ int ot_fmm_l2l(ot_fmm_tree tree, const double* Lp, const double* comp, const dou
     if (rc) return rc;
     if (!aligned16(Lp) || !aligned16(comp) || !aligned16(comc) || !aligned16(Lc))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    {
+        const int64_t nc = (int64_t)tree->Sc * kSub3, np = (int64_t)tree->Sp * kSub3;
+        if (overlap(Lc, 20 * nc, Lp, 20 * np) || overlap(Lc, 20 * nc, comp, 3 * np) ||
+            overlap(Lc, 20 * nc, comc, 3 * nc))
+            return fail(OT_FMM_EINVAL, "Lc overlaps an input");
+    }
     TreeParams tp{};
     tp.children = tree->d_children;
     tp.m_in = Lp;
@@ -381,6 +395,9 @@ int ot_fmm_evaluate(int64_t ncells, const double* M, const double* L, double* F,
     if (ncells <= 0 || ncells > ((int64_t)1 << 38)) return fail(OT_FMM_EINVAL, "ncells out of range");
     if (!aligned16(M) || !aligned16(L) || !aligned16(F) || !aligned16(W))
         return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (overlap(F, 3 * ncells, M, 20 * ncells) || overlap(F, 3 * ncells, L, 20 * ncells) ||
+        overlap(W, ncells, M, 20 * ncells) || overlap(W, ncells, L, 20 * ncells) || overlap(F, 3 * ncells, W, ncells))
+        return fail(OT_FMM_EINVAL, "outputs overlap inputs or each other");
     int rc = ensure_device();
     if (rc) return rc;
     hipLaunchKernelGGL(k_evaluate, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0,

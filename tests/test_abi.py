@@ -138,3 +138,22 @@ def test_evaluate_rejects_bad_sizes(lib):
     base = ctypes.addressof(buf)
     assert lib.ot_fmm_evaluate(0, base, base, base, base, None) == -1
     assert lib.ot_fmm_evaluate(4, None, base, base, base, None) == -1
+
+
+def test_overlapping_outputs_rejected_before_any_device_call(lib):
+    """Output ranges that overlap inputs are EINVAL (checked from the extents,
+    before the device is touched, so this runs without a GPU)."""
+    P = ctypes.c_void_p
+    buf = (ctypes.c_double * (30 * 13824))()
+    base = ctypes.addressof(buf)
+    base += (-base) % 16
+    lib.ot_fmm_multipole.argtypes = [P, P, P, P]
+    lib.ot_fmm_monopole.argtypes = [P, P, P, P]
+    M, com = base, base + 20 * 13824 * 8
+    assert lib.ot_fmm_multipole(M, com, M + 8 * 512 * 4, None) == -1          # L inside M
+    assert lib.ot_fmm_monopole(M, com, com + 16, None) == -1                   # L inside com
+    lib.ot_fmm_evaluate.argtypes = [ctypes.c_int64, P, P, P, P, P]
+    n = 1024
+    Mv, Lv = base, base + 20 * n * 8
+    assert lib.ot_fmm_evaluate(n, Mv, Lv, Lv + 16 * 8, base + 60 * n * 8, None) == -1  # F inside L
+    assert lib.ot_fmm_evaluate(n, Mv, Lv, base + 40 * n * 8, base + 41 * n * 8, None) == -1  # W inside F
