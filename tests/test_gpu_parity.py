@@ -378,3 +378,27 @@ def test_config5_step_graph_sampled():
     print("config5 gM worst", assert_parity(gMs, gM_ref, TOL, what="config5 gM"))
     print("config5 gX worst", assert_parity(gXs, gX_ref, TOL, what="config5 gX"))
     assert bool(torch.isfinite(L).all()) and bool(torch.isfinite(gM).all()) and bool(torch.isfinite(gX).all())
+
+
+def test_overlapping_outputs_rejected(ot):
+    """An output whose range overlaps an input is refused with EINVAL and
+    nothing is written."""
+    import torch
+    batch, M, X = synthetic.batched_config(2, 93)
+    plan = ot.Plan.from_batch(batch)
+    NS, NT = batch["S"] * 512, batch["T"] * 512
+    Md, Xd = _dev(M), _dev(X)
+    big = torch.zeros(40 * NS, dtype=torch.float64, device="cuda")
+    L_in_M = big[: 20 * NT].view(20, NT)
+    Mb = big[8 * 512: 8 * 512 + 20 * NS].view(20, NS)   # M shifted by one sub-grid into the same buffer
+    Mb.copy_(Md)
+    with pytest.raises(ot.OtFmmError) as e:
+        plan.multipole_batched(Mb, Xd, L_in_M)
+    assert e.value.code == ot.OT_FMM_EINVAL
+    w = _dev(synthetic.weights(batch["T"], 94))
+    gX = _empty(3, NS)
+    with pytest.raises(ot.OtFmmError) as e:
+        plan.multipole_backward(Md, Xd, w, w.view(-1)[: 20 * NS].view(20, NS) if NT >= NS else w, gX)
+    assert e.value.code == ot.OT_FMM_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(Mb, Md)  # untouched
