@@ -4,6 +4,7 @@ and rejects invalid arguments on the host before touching a device. CPU only
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -157,3 +158,16 @@ def test_overlapping_outputs_rejected_before_any_device_call(lib):
     Mv, Lv = base, base + 20 * n * 8
     assert lib.ot_fmm_evaluate(n, Mv, Lv, Lv + 16 * 8, base + 60 * n * 8, None) == -1  # F inside L
     assert lib.ot_fmm_evaluate(n, Mv, Lv, base + 40 * n * 8, base + 41 * n * 8, None) == -1  # W inside F
+
+
+def test_package_refuses_to_import_without_the_library(tmp_path):
+    """No fallback: a copy of the package without libotfmm.so fails to import."""
+    import shutil
+    import subprocess
+    src = os.path.join(ROOT, "paper_2303_08058_amd", "__init__.py")
+    pkg = tmp_path / "paper_2303_08058_amd"
+    pkg.mkdir()
+    shutil.copy(src, pkg / "__init__.py")
+    r = subprocess.run([sys.executable, "-c", "import paper_2303_08058_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "libotfmm.so is not built" in r.stderr
