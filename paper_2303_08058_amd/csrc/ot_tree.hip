@@ -116,14 +116,21 @@ __device__ __forceinline__ double quad_sum(double v)
 // (lane = x + 8 y; cells (x, y, 2Z) and (x, y, 2Z + 1)), so every load is one
 // contiguous 512-byte row. The 8 children of a parent cell are the two cells
 // of lanes l, l^1, l^8 and l^9, summed by cross-lane exchange; each of those
-// four lanes then stores 5 of the 20 parent moments.
+// four lanes then puts 5 of the 20 parent moments into LDS, where the four
+// wavefronts of the work-group assemble one full 8x8 parent plane that is
+// stored as 512-byte rows (directly from the lanes, the stores were 32-byte
+// pieces and the pass 20% slower).
 __global__ void __launch_bounds__(256) k_m2m(const TreeParams p)
 {
-    // wave index, kept in scalar registers so that the child lookup is a scalar load
-    const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= (long)p.Sp * 32) return;  // whole wavefronts: 8 octants x 4 z-pairs per parent
+    // work-group = one z-plane of a parent node (8 per node): its 4 wavefronts
+    // are the 4 child octants below that plane (one z-pair of cells each); the
+    // indices are wave-uniform (scalar registers, scalar child lookup)
+    const long blk = blockIdx.x;
+    if (blk >= (long)p.Sp * 8) return;  // whole work-groups
     const int lane = threadIdx.x & 63;
-    const int node = (int)(w >> 5), o = (int)((w >> 2) & 7), Z = (int)(w & 3);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int node = (int)(blk >> 3), oz = (int)((blk >> 2) & 1), Z = (int)(blk & 3);
+    const int o = wave + 4 * oz;
     const long j0 = (long)p.children[node * 8 + o] * kSub3 + 128 * Z + lane;
     const long j1 = j0 + 64;
     const long nc = p.n_child;
@@ -158,19 +165,28 @@ __global__ void __launch_bounds__(256) k_m2m(const TreeParams p)
 #pragma unroll
     for (int b = 0; b < 20; ++b) acc[b] = quad_sum(acc[b]);
 
+    // the 8x8 parent cells of the plane gather in LDS, so that every store
+    // is one contiguous 512-byte row
+    __shared__ double s_out[23][64];
     const int x = lane & 7, y = lane >> 3;
     const int q = (x & 1) + 2 * (y & 1);
-    const int pc = (x >> 1) + 4 * (o & 1) + 8 * ((y >> 1) + 4 * ((o >> 1) & 1)) +
-                   64 * (Z + 4 * (o >> 2));
-    const long np = p.n_parent;
-    const long out = (long)node * kSub3 + pc;
+    const int cp = (x >> 1) + 4 * (o & 1) + 8 * ((y >> 1) + 4 * ((o >> 1) & 1));  // cell in the plane
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
         const double v = q == 0 ? acc[4 * i] : q == 1 ? acc[4 * i + 1] : q == 2 ? acc[4 * i + 2]
                                                                                   : acc[4 * i + 3];
-        p.m_out[(4 * i + q) * np + out] = v;
+        s_out[4 * i + q][cp] = v;
     }
-    if (q < 3) p.x_out[q * np + out] = q == 0 ? c[0] : q == 1 ? c[1] : c[2];
+    if (q < 3) s_out[20 + q][cp] = q == 0 ? c[0] : q == 1 ? c[1] : c[2];
+    __syncthreads();
+    const long np = p.n_parent;
+    const long base = (long)node * kSub3 + 64 * (Z + 4 * oz) + lane;
+    for (int comp = wave; comp < 23; comp += 4) {
+        if (comp < 20)
+            p.m_out[comp * np + base] = s_out[comp][lane];
+        else
+            p.x_out[(comp - 20) * np + base] = s_out[comp][lane];
+    }
 }
 
 // L_A(child) += sum_{|G| <= 3 - |A|} L_{A+G}(parent) d^G / G!
@@ -353,7 +369,7 @@ int ot_fmm_m2m(ot_fmm_tree tree, const double* Mc, const double* comc, double* M
     tp.n_child = (long)tree->Sc * kSub3;
     tp.n_parent = (long)tree->Sp * kSub3;
     tp.Sp = tree->Sp;
-    // 32 wavefronts per parent node, 4 per work-group
+    // 8 work-groups of 4 wavefronts per parent node
     hipLaunchKernelGGL(k_m2m, dim3((unsigned)tree->Sp * 8), dim3(256), 0, (hipStream_t)stream, tp);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
