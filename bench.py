@@ -103,8 +103,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the kernels shard by sub-grid; "
-              "multi-GPU runs are not part of it). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (sharding the sub-grids over GPUs "
+              "is a design note, not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
