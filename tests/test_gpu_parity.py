@@ -402,3 +402,53 @@ def test_overlapping_outputs_rejected(ot):
     assert e.value.code == ot.OT_FMM_EINVAL
     torch.cuda.synchronize()
     assert torch.equal(Mb, Md)  # untouched
+
+
+@pytest.mark.parametrize("sched", [0x22, 0x12])
+def test_concurrent_launches_of_one_plan_on_two_streams(ot, sched):
+    """Two forward launches of the same plan in flight at once on two streams
+    (persistent launches take separate counter slots) give the eager result."""
+    import torch
+    batch, M, X = synthetic.batched_config(3, 95, missing_frac=0.3)
+    plan = ot.Plan.from_batch(batch)
+    NT = batch["T"] * 512
+    Md, Xd = _dev(M), _dev(X)
+    ref = _empty(20, NT)
+    plan.multipole_batched(Md, Xd, ref, sched=2)
+    torch.cuda.synchronize()
+    outs = [_empty(20, NT) for _ in range(4)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for k, L in enumerate(outs):
+        plan.multipole_batched(Md, Xd, L, sched=sched, stream=streams[k % 2])
+    torch.cuda.synchronize()
+    for L in outs:
+        assert torch.equal(L, ref)
+
+
+@pytest.mark.parametrize("sched", [0x22, 0x12])
+def test_caller_captured_graph_replays(ot, sched):
+    """The batched forward captured into a caller's graph (torch.cuda.CUDAGraph)
+    replays correctly several times, with eager work in between (the
+    persistent form records its counter reset as a kernel node)."""
+    import torch
+    batch, M, X = synthetic.batched_config(3, 96, missing_frac=0.3)
+    plan = ot.Plan.from_batch(batch)
+    NT = batch["T"] * 512
+    Md, Xd = _dev(M), _dev(X)
+    ref = _empty(20, NT)
+    plan.multipole_batched(Md, Xd, ref, sched=sched)
+    L = _empty(20, NT)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.multipole_batched(Md, Xd, L, sched=sched, stream=s)
+    for rep in range(3):
+        L.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(L, ref), rep
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        del junk
