@@ -332,6 +332,81 @@ int orc_batched_forward(int S, int T, const int32_t *tgt, const int32_t *nbr,
     return 0;
 }
 
+/* Coarse substitute for missing neighbours -- a reading: the paper gives no
+ * FMM formulas; at a refinement boundary an FMM lets fine cells interact with
+ * the coarser cells that cover a region holding no fine cells.
+ * For target t and a slot s whose fine sub-grid is missing, coarse[t][s] is
+ * the parent-level node P and octant[t][s] = o the octant of P that covers
+ * the missing block (halo cells 8 s_k .. 8 s_k + 7 per axis). Its 4^3 coarse
+ * cells J are the parents of the 2x2x2 fine cells j = 8 s_k + 2 J_k + {0, 1}.
+ * Target cell i interacts with J iff all 8 of those fine cells are in S(i);
+ * J then stands in for them, with its own moments about its own centre:
+ *   L_a(i) += sum_{|b| <= 3-|a|} s_b M_b(J) G_{a+b}(X_i - X_J - shift(t, s)).
+ * A J with some child near i is left out, like every near pair.
+ * Mp[20][Sp*512], Xp[3][Sp*512]: coarse store; coarse cell (cx, cy, cz) of
+ * octant o is cell (cx + 4 o_x) + 8 (cy + 4 o_y) + 64 (cz + 4 o_z) of P.
+ * Returns the coarse contributions only, L (20, nsel*512), for targets tsel. */
+int orc_coarse_fine(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
+                    const double *period, const double *X, int Sp, const int32_t *coarse,
+                    const int8_t *octant, const double *Mp, const double *Xp,
+                    const int32_t *tsel, int nsel, double *L, double *Aabs, int nthreads)
+{
+    init_tables();
+    if (check_batch(S, T, tgt, nbr) || Sp <= 0 || !coarse || !octant) return -1;
+    for (int t = 0; t < T; ++t)
+        for (int s = 0; s < 27; ++s) {
+            int c = coarse[t * 27 + s];
+            if (c < -1 || c >= Sp) return -1;
+            if (c >= 0 && (s == 13 || nbr[t * 27 + s] >= 0)) return -1;
+            if (c >= 0 && (octant[t * 27 + s] < 0 || octant[t * 27 + s] > 7)) return -1;
+        }
+    for (int q = 0; q < nsel; ++q)
+        if (tsel[q] < 0 || tsel[q] >= T) return -1;
+    const size_t NS = (size_t)S * SUB3, NP = (size_t)Sp * SUB3, NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int q = 0; q < nsel; ++q)
+        for (int ci = 0; ci < SUB3; ++ci) {
+            int t = tsel[q];
+            int li[3];
+            local_coords(ci, li);
+            int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+            size_t iidx = (size_t)tgt[t] * SUB3 + ci;
+            double Xi[3] = {X[iidx], X[NS + iidx], X[2 * NS + iidx]};
+            double acc[NM] = {0}, aabs[NM] = {0};
+            for (int slot = 0; slot < 27; ++slot) {
+                int P = coarse[t * 27 + slot];
+                if (P < 0) continue;
+                int o = octant[t * 27 + slot], so[3];
+                slot_coords(slot, so);
+                double sh[3];
+                neighbour_shift(shift, period, t, slot, sh);
+                for (int J = 0; J < 64; ++J) {
+                    int cj[3] = {J % 4, (J / 4) % 4, J / 16};
+                    int all_in = 1;
+                    for (int n = 0; n < 8 && all_in; ++n) {
+                        int hj[3] = {8 * so[0] + 2 * cj[0] + (n & 1), 8 * so[1] + 2 * cj[1] + ((n >> 1) & 1),
+                                     8 * so[2] + 2 * cj[2] + (n >> 2)};
+                        all_in = in_stencil(hi, hj);
+                    }
+                    if (!all_in) continue;
+                    int pc = (cj[0] + 4 * (o & 1)) + SUB * (cj[1] + 4 * ((o >> 1) & 1)) +
+                             SUB * SUB * (cj[2] + 4 * (o >> 2));
+                    size_t jidx = (size_t)P * SUB3 + pc;
+                    double Xj[3] = {Xp[jidx] + sh[0], Xp[NP + jidx] + sh[1], Xp[2 * NP + jidx] + sh[2]};
+                    double Mj[NM];
+                    for (int b = 0; b < NM; ++b) Mj[b] = Mp[b * NP + jidx];
+                    pair_forward_re(Xi, Xj, Mj, NM, 3, acc, Aabs ? aabs : NULL);
+                }
+            }
+            for (int a = 0; a < NM; ++a) {
+                L[a * NO + (size_t)q * SUB3 + ci] = acc[a];
+                if (Aabs) Aabs[a * NO + (size_t)q * SUB3 + ci] = aabs[a];
+            }
+        }
+    return 0;
+}
+
 /* Same sum with complex centres of mass X = Xre + i Xim (moments real), for
  * complex-step differentiation: d(sum w L)/dX_c,k = Im(sum w L(X + i h e_ck))/h. */
 int orc_batched_forward_cs(int S, int T, const int32_t *tgt, const int32_t *nbr,

@@ -228,6 +228,25 @@ def octree_children(n):
     return (c[..., 0] + n * c[..., 1] + n * n * c[..., 2]).astype(np.int32)
 
 
+def coarse_tables(n, batch):
+    """Coarse substitutes of the missing neighbours of a lattice batch over an
+    n^3 store (n even) whose parent level is octree_children(n): for each
+    target t and slot s missing in `batch` but present in the full lattice,
+    (coarse node P, octant o) of the parent that covers the missing
+    sub-grid; -1 elsewhere. Returns int32 (T, 27), int8 (T, 27)."""
+    assert n % 2 == 0
+    m = n // 2
+    full = lattice_batch(n, periodic=batch.get("period") is not None)["nbr"]
+    nbr = np.asarray(batch["nbr"])
+    b = np.where((nbr < 0) & (full >= 0), full, -1)
+    bx, by, bz = b % n, (b // n) % n, b // (n * n)
+    P = (bx // 2) + m * (by // 2) + m * m * (bz // 2)
+    o = (bx % 2) + 2 * (by % 2) + 4 * (bz % 2)
+    coarse = np.where(b >= 0, P, -1).astype(np.int32)
+    octant = np.where(b >= 0, o, 0).astype(np.int8)
+    return coarse, octant
+
+
 def local_field(ncell, rng, h=1.0):
     """Synthetic local expansion coefficients L (20, ncell): N(0, 1) scaled by
     h^-|a| (the size of a derivative of order |a| of a smooth potential)."""
