@@ -67,6 +67,10 @@ _lib.ot_fmm_plan_destroy.argtypes = [_P]
 _lib.ot_fmm_plan_destroy.restype = _I
 _lib.ot_fmm_plan_pairs.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
 _lib.ot_fmm_plan_pairs.restype = _I
+_lib.ot_fmm_plan_set_coarse.argtypes = [_P, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64)]
+_lib.ot_fmm_plan_set_coarse.restype = _I
+_lib.ot_fmm_coarse_fine.argtypes = [_P, _P, _P, _P, _P, _P]
+_lib.ot_fmm_coarse_fine.restype = _I
 _lib.ot_fmm_multipole_batched.argtypes = [_P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_batched.restype = _I
 _lib.ot_fmm_multipole_backward.argtypes = [_P, _P, _P, _P, _P, _P, _I, _P]
@@ -246,6 +250,34 @@ class Plan:
         _check(_lib.ot_fmm_plan_pairs(self.handle, ctypes.byref(v)), "ot_fmm_plan_pairs")
         return int(v.value)
 
+    def set_coarse(self, Sp, coarse, octant) -> int:
+        """Coarse substitutes for missing neighbours: coarse (T, 27) node of a
+        coarse store of Sp nodes (-1: none) and octant (T, 27) of that node
+        covering the missing block. Returns the included (target cell, coarse
+        cell) pairs."""
+        coarse = np.ascontiguousarray(coarse, dtype=np.int32)
+        octant = np.ascontiguousarray(octant, dtype=np.int8)
+        if coarse.shape != (self.T, 27) or octant.shape != (self.T, 27):
+            raise ValueError("coarse and octant must be (T, 27)")
+        v = ctypes.c_int64()
+        _check(_lib.ot_fmm_plan_set_coarse(self.handle, int(Sp), coarse.ctypes.data_as(_P),
+                                           octant.ctypes.data_as(_P), ctypes.byref(v)),
+               "ot_fmm_plan_set_coarse")
+        self.Sp_coarse = int(Sp)
+        return int(v.value)
+
+    def coarse_fine(self, com, Mp, comp, L, stream=None):
+        """Adds the coarse substitutes' contributions into L (20, T*512)."""
+        Sp = getattr(self, "Sp_coarse", 0)
+        if Sp <= 0:
+            raise ValueError("no coarse substitutes set")
+        _, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_coarse_fine(self.handle, _dptr(com, sx, "com"),
+                                       _dptr(Mp, (20, Sp * 512), "Mp"),
+                                       _dptr(comp, (3, Sp * 512), "comp"), _dptr(L, sl, "L"),
+                                       _stream(stream)), "ot_fmm_coarse_fine")
+        return L
+
     def _shapes(self):
         NS, NT = self.S * 512, self.T * 512
         return (20, NS), (3, NS), (20, NT)
@@ -305,6 +337,14 @@ def ot_fmm_multipole_batched(plan, M, com, L, sched=SCHED_AUTO, stream=None):
 
 def ot_fmm_multipole_backward(plan, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
     return plan.multipole_backward(M, com, gL, gM, gcom, sched, stream)
+
+
+def ot_fmm_plan_set_coarse(plan, Sp, coarse, octant):
+    return plan.set_coarse(Sp, coarse, octant)
+
+
+def ot_fmm_coarse_fine(plan, com, Mp, comp, L, stream=None):
+    return plan.coarse_fine(com, Mp, comp, L, stream)
 
 
 class MultipoleBatched(torch.autograd.Function):

@@ -52,6 +52,7 @@
 #include "ot_host.h"
 #include "ot_fmm.h"
 #include "ot_interact.h"
+#include "ot_coarse.h"
 
 
 // ===========================================================================
@@ -162,6 +163,12 @@ struct ot_fmm_plan_s {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[3];
     size_t ev_used[3] = {0, 0, 0};
+    // coarse substitutes for missing neighbours (ot_fmm_plan_set_coarse)
+    std::vector<uint32_t> missing;  // [T] bit s: slot s has no fine neighbour
+    int32_t Sp_coarse = 0;
+    int n_coarse_targets = 0;
+    int2* d_coarse = nullptr;       // [T][27] {coarse node, octant}
+    int* d_coarse_list = nullptr;   // targets with substitutes, most first
 };
 
 namespace {
@@ -348,6 +355,10 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_fwd_local);
     (void)hipFree(p->d_rev_local);
     (void)hipFree(p->d_counters);
+    (void)hipFree(p->d_coarse);
+    (void)hipFree(p->d_coarse_list);
+    p->d_coarse = nullptr;
+    p->d_coarse_list = nullptr;
 }
 
 // Work order: longest work first (a greedy longest-processing-time list for
@@ -633,6 +644,10 @@ int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
     if (period)
         for (int k = 0; k < 3; ++k) p->period[k] = period[k];
     p->pairs = pairs;
+    p->missing.assign(T, 0u);
+    for (int t = 0; t < T; ++t)
+        for (int q = 0; q < 27; ++q)
+            if (nbr[(int64_t)t * 27 + q] < 0) p->missing[t] |= 1u << q;
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, p->device)) != hipSuccess) {
         delete p;
@@ -707,6 +722,101 @@ int ot_fmm_stencil_info(int64_t* slot_pairs, int32_t* offsets_per_target, int32_
     }
     if (!sc.mirror_ok) return fail(OT_FMM_EUNSUPPORTED, "stencil mirror check failed");
     return OT_FMM_OK;
+}
+
+int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, const int8_t* octant,
+                           int64_t* pairs)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (Sp <= 0 || !coarse || !octant) return fail(OT_FMM_EINVAL, "Sp > 0, coarse and octant required");
+    if ((int64_t)Sp * kSub3 * 20 > ((int64_t)1 << 40)) return fail(OT_FMM_EINVAL, "coarse store too large");
+    const int T = plan->T;
+    std::vector<int2> tab((size_t)T * 27);
+    std::vector<int> count(T, 0);
+    for (int t = 0; t < T; ++t)
+        for (int q = 0; q < 27; ++q) {
+            const int32_t c = coarse[(int64_t)t * 27 + q];
+            const int o = octant[(int64_t)t * 27 + q];
+            if (c < -1 || c >= Sp) return fail(OT_FMM_EINVAL, "coarse node out of range");
+            if (c >= 0 && !((plan->missing[t] >> q) & 1u))
+                return fail(OT_FMM_EINVAL, "a substitute is given for a neighbour that is present");
+            if (c >= 0 && (o < 0 || o > 7)) return fail(OT_FMM_EINVAL, "octant out of range");
+            tab[(size_t)t * 27 + q] = make_int2(c, c >= 0 ? o : 0);
+            count[t] += c >= 0;
+        }
+    // included (target cell, coarse cell) pairs per slot: geometry only
+    int64_t slot_pairs[27] = {0};
+    for (int q = 0; q < 27; ++q) {
+        const int so[3] = {q % 3, (q / 3) % 3, q / 9};
+        for (int c = 0; c < kSub3; ++c) {
+            const int hi[3] = {8 + c % 8, 8 + (c / 8) % 8, 8 + c / 64};
+            for (int J = 0; J < 64; ++J) {
+                const int cj[3] = {J & 3, (J >> 2) & 3, J >> 4};
+                bool all_in = true;
+                for (int n = 0; n < 8 && all_in; ++n)
+                    all_in = criterion(hi[0], hi[1], hi[2], 8 * so[0] + 2 * cj[0] + (n & 1),
+                                       8 * so[1] + 2 * cj[1] + ((n >> 1) & 1), 8 * so[2] + 2 * cj[2] + (n >> 2));
+                slot_pairs[q] += all_in;
+            }
+        }
+    }
+    int64_t total = 0;
+    std::vector<int> list;
+    for (int t = 0; t < T; ++t) {
+        if (count[t]) list.push_back(t);
+        for (int q = 0; q < 27; ++q)
+            if (tab[(size_t)t * 27 + q].x >= 0) total += slot_pairs[q];
+    }
+    std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return count[a] > count[b]; });
+    int2* d_tab = nullptr;
+    int* d_list = nullptr;
+    if ((rc = upload(&d_tab, tab)) || (rc = upload(&d_list, list))) {
+        (void)hipFree(d_tab);
+        (void)hipFree(d_list);
+        return rc;
+    }
+    (void)hipFree(plan->d_coarse);
+    (void)hipFree(plan->d_coarse_list);
+    plan->d_coarse = d_tab;
+    plan->d_coarse_list = d_list;
+    plan->Sp_coarse = Sp;
+    plan->n_coarse_targets = (int)list.size();
+    if (pairs) *pairs = total;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp, double* L,
+                       void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (plan->Sp_coarse <= 0) return fail(OT_FMM_EINVAL, "no coarse substitutes set (ot_fmm_plan_set_coarse)");
+    if (!aligned16(com) || !aligned16(Mp) || !aligned16(comp) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3,
+                  NP = (int64_t)plan->Sp_coarse * kSub3;
+    if (overlap(L, 20 * NT, com, 3 * NS) || overlap(L, 20 * NT, Mp, 20 * NP) || overlap(L, 20 * NT, comp, 3 * NP))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    if (plan->n_coarse_targets == 0) return OT_FMM_OK;
+    CoarseParams cp{};
+    cp.pos = com;
+    cp.pos_stride = NS;
+    cp.mom_c = Mp;
+    cp.pos_c = comp;
+    cp.c_stride = NP;
+    cp.list = plan->d_coarse_list;
+    cp.coarse = plan->d_coarse;
+    cp.rel = plan->d_fwd_rel;
+    cp.own_blk = plan->d_tgt;
+    cp.out = L;
+    cp.out_stride = NT;
+    for (int k = 0; k < 3; ++k) cp.period[k] = plan->period[k];
+    hipLaunchKernelGGL(k_coarse_fine, dim3((unsigned)plan->n_coarse_targets), dim3(512), 0, (hipStream_t)stream, cp);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
 }
 
 int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs)
