@@ -199,7 +199,8 @@ def main():
     # ----------------------------------------- tree passes on the same store
     tree = None
     if args.tree_steps > 0 and args.n % 2 == 0:
-        tree = tree_passes(args.n, args.tree_steps, Md, Xd, L, ot, synthetic, np, torch, dev)
+        tree = tree_passes(args.n, args.tree_steps, Md, Xd, L, ot, synthetic, np, torch, dev,
+                           plan=plan, batch=batch)
 
     # --------------------------------------- batched vs per-sub-grid launches
     per_sub = None
@@ -268,10 +269,12 @@ TREE_BYTES = {"m2m": 1656, "l2l": 367, "evaluate": 352}
 PEAK_HBM_GBS = 8000.0
 
 
-def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev):
+def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev, plan=None, batch=None):
     """Times the upward pass from the n^3 store to its (n/2)^3 parent level,
-    the downward pass back into the store's coefficients, and the local
-    evaluation over every cell; HIP events on the launch stream."""
+    the downward pass back into the store's coefficients, the local
+    evaluation over every cell and, with a plan, the coarse substitutes of
+    its missing neighbours (taken from the parent level the upward pass
+    wrote); HIP events on the launch stream."""
     ch = synthetic.octree_children(n)
     Sp, S = ch.shape[0], n ** 3
     tree = ot.Tree(ch, S)
@@ -307,6 +310,30 @@ def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev):
                                   "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}}
         log("tree %-9s %.3f ms  %.0f GB/s" % (name, ms, gbs))
     tree.close()
+    if plan is not None:
+        coarse, octant = synthetic.coarse_tables(n, batch)
+        cpairs = plan.set_coarse(Sp, coarse, octant)
+        ntg = int((coarse >= 0).any(1).sum())
+        for _ in range(2):
+            plan.coarse_fine(Xd, Mp, Xp, L)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.coarse_fine(Xd, Mp, Xp, L)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tf = cpairs * FLOP_PER_PAIR["forward"] / (ms * 1e-3) / 1e12
+        out["coarse_fine"] = {
+            "mean_ms": round(ms, 4), "targets": ntg, "substituted_slots": int((coarse >= 0).sum()),
+            "pairs": cpairs, "unit": "(target cell, coarse cell) pair",
+            "flop_per_pair": FLOP_PER_PAIR["forward"],
+            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)}}
+        log("coarse_fine     %.3f ms  %d targets, %d pairs, %.2f TFLOP/s"
+            % (ms, ntg, cpairs, tf))
     # a plain device copy of 2 GiB on the same stream, as the attainable
     # read+write bandwidth these streaming kernels compare with
     a = torch.empty(1 << 28, **f64)

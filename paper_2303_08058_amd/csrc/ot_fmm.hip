@@ -168,7 +168,9 @@ struct ot_fmm_plan_s {
     int32_t Sp_coarse = 0;
     int n_coarse_targets = 0;
     int2* d_coarse = nullptr;       // [T][27] {coarse node, octant}
-    int* d_coarse_list = nullptr;   // targets with substitutes, most first
+    int* d_coarse_list = nullptr;   // targets with substitutes, most work first
+    int* d_lane_cell = nullptr;     // [27][512] target cell of each lane, per slot
+    unsigned long long* d_lane_mask = nullptr;  // [27][512] included coarse cells
 };
 
 namespace {
@@ -357,8 +359,12 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_counters);
     (void)hipFree(p->d_coarse);
     (void)hipFree(p->d_coarse_list);
+    (void)hipFree(p->d_lane_cell);
+    (void)hipFree(p->d_lane_mask);
     p->d_coarse = nullptr;
     p->d_coarse_list = nullptr;
+    p->d_lane_cell = nullptr;
+    p->d_lane_mask = nullptr;
 }
 
 // Work order: longest work first (a greedy longest-processing-time list for
@@ -746,10 +752,16 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
             tab[(size_t)t * 27 + q] = make_int2(c, c >= 0 ? o : 0);
             count[t] += c >= 0;
         }
-    // included (target cell, coarse cell) pairs per slot: geometry only
-    int64_t slot_pairs[27] = {0};
+    // per slot (geometry only): the coarse cells included for each target
+    // cell as a 64-bit mask, the cells in lane order (most included first),
+    // the included pairs and the loop trips of the 8 wavefronts
+    std::vector<unsigned long long> lane_mask((size_t)27 * kSub3);
+    std::vector<int> lane_cell((size_t)27 * kSub3);
+    int64_t slot_pairs[27] = {0}, slot_cost[27] = {0};
     for (int q = 0; q < 27; ++q) {
         const int so[3] = {q % 3, (q / 3) % 3, q / 9};
+        std::vector<unsigned long long> m(kSub3, 0ull);
+        std::vector<int> cnt(kSub3, 0), order(kSub3);
         for (int c = 0; c < kSub3; ++c) {
             const int hi[3] = {8 + c % 8, 8 + (c / 8) % 8, 8 + c / 64};
             for (int J = 0; J < 64; ++J) {
@@ -758,25 +770,49 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
                 for (int n = 0; n < 8 && all_in; ++n)
                     all_in = criterion(hi[0], hi[1], hi[2], 8 * so[0] + 2 * cj[0] + (n & 1),
                                        8 * so[1] + 2 * cj[1] + ((n >> 1) & 1), 8 * so[2] + 2 * cj[2] + (n >> 2));
-                slot_pairs[q] += all_in;
+                if (all_in) {
+                    m[c] |= 1ull << J;
+                    ++cnt[c];
+                }
             }
+            slot_pairs[q] += cnt[c];
+            order[c] = c;
         }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+        for (int l = 0; l < kSub3; ++l) {
+            lane_cell[(size_t)q * kSub3 + l] = order[l];
+            lane_mask[(size_t)q * kSub3 + l] = m[order[l]];
+        }
+        for (int w = 0; w < kSub3 / 64; ++w) slot_cost[q] += cnt[order[64 * w]];
     }
     int64_t total = 0;
     std::vector<int> list;
+    std::vector<int64_t> cost(T, 0);
     for (int t = 0; t < T; ++t) {
         if (count[t]) list.push_back(t);
         for (int q = 0; q < 27; ++q)
-            if (tab[(size_t)t * 27 + q].x >= 0) total += slot_pairs[q];
+            if (tab[(size_t)t * 27 + q].x >= 0) {
+                total += slot_pairs[q];
+                cost[t] += slot_cost[q] + 4;  // + staging
+            }
     }
-    std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return count[a] > count[b]; });
+    std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     int2* d_tab = nullptr;
     int* d_list = nullptr;
-    if ((rc = upload(&d_tab, tab)) || (rc = upload(&d_list, list))) {
+    int* d_cell = nullptr;
+    unsigned long long* d_mask = nullptr;
+    if ((rc = upload(&d_tab, tab)) || (rc = upload(&d_list, list)) || (rc = upload(&d_cell, lane_cell)) ||
+        (rc = upload(&d_mask, lane_mask))) {
         (void)hipFree(d_tab);
         (void)hipFree(d_list);
+        (void)hipFree(d_cell);
+        (void)hipFree(d_mask);
         return rc;
     }
+    (void)hipFree(plan->d_lane_cell);
+    (void)hipFree(plan->d_lane_mask);
+    plan->d_lane_cell = d_cell;
+    plan->d_lane_mask = d_mask;
     (void)hipFree(plan->d_coarse);
     (void)hipFree(plan->d_coarse_list);
     plan->d_coarse = d_tab;
@@ -811,6 +847,8 @@ int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, co
     cp.coarse = plan->d_coarse;
     cp.rel = plan->d_fwd_rel;
     cp.own_blk = plan->d_tgt;
+    cp.lane_cell = plan->d_lane_cell;
+    cp.lane_mask = plan->d_lane_mask;
     cp.out = L;
     cp.out_stride = NT;
     for (int k = 0; k < 3; ++k) cp.period[k] = plan->period[k];
