@@ -483,11 +483,32 @@ def cpu_baseline(batch, M, X, w, seconds, np):
             break
         k = 2 * k if spent < seconds / 4 else k
     log("cpu oracle: %d sub-grids, %.1f s, %d threads" % (used, spent, max_threads()))
+    # one thread on the first sampled sub-grid: the per-core rate
+    sel = order[:1].astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.batched_forward(batch, M, X, tsel=sel, nthreads=1)
+    oracle.batched_backward(batch, M, X, w, ssel=sel, nthreads=1)
+    one = time.perf_counter() - t0
+    one_pairs = int(sum(slot_pairs[s] for s in range(27) if nbr[sel[0], s] >= 0))
+    log("cpu oracle, one thread: %.1f s" % one)
     return {"value": pairs / spent, "unit": "cell-pair interactions/s", "cores": max_threads(),
             "kind": "oracle",
             "sample": "fwd of %d sampled target sub-grids + adjoint of the same %d store "
                       "sub-grids of the benchmark workload (%d pairs, %.1f s)"
-                      % (used, used, pairs, spent)}
+                      % (used, used, pairs, spent),
+            "one_core_value": one_pairs / one,
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _slot_pairs(np):

@@ -174,10 +174,15 @@ static void local_coords(int c, int l[3])
 #undef FN
 #undef cabs_generic
 
+/* nthreads > 0: that many threads for this call; 0: the process default
+ * (OMP_NUM_THREADS or all cores), also after a call that asked for fewer. */
+static int g_default_threads = 0;
+
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    if (g_default_threads == 0) g_default_threads = omp_get_max_threads();
+    omp_set_num_threads(nthreads > 0 ? nthreads : g_default_threads);
 #else
     (void)nthreads;
 #endif
@@ -205,7 +210,7 @@ int orc_in_stencil(const int hi[3], const int hj[3]) { return in_stencil(hi, hj)
 int orc_max_threads(void)
 {
 #ifdef _OPENMP
-    return omp_get_max_threads();
+    return g_default_threads ? g_default_threads : omp_get_max_threads();
 #else
     return 1;
 #endif
