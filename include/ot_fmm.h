@@ -157,8 +157,9 @@ int ot_fmm_work_orders(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
  * every parity (the kernels then refuse to run). */
 int ot_fmm_stencil_info(int64_t* slot_pairs, int32_t* offsets_per_target, int32_t* rows_per_parity);
 
-/* Coarse substitutes for missing neighbours (a reading of an FMM at a
- * refinement boundary; the paper gives no FMM formulas). For target t and a
+/* Coarse substitutes for missing neighbours. Sec. 2.1 names the octree FMM
+ * gravity solver without its formulas; what follows is a reading of the
+ * interaction across a refinement boundary. For target t and a
  * slot s whose fine neighbour is missing (nbr[t][s] == -1), coarse[t][s] is
  * the node P of a coarse store and octant[t][s] = o the octant of P that
  * covers the missing block; -1 where there is none. Coarse cell
@@ -170,14 +171,19 @@ int ot_fmm_stencil_info(int64_t* slot_pairs, int32_t* offsets_per_target, int32_
  *   L_a(i) += sum_{|b| <= 3-|a|} s_b M_b(J) G_{a+b}(X_i - X_J).
  * set_coarse: HOST tables [T][27] (EINVAL: node out of [-1, Sp), a
  * substitute for a present neighbour, octant out of [0, 8)); keeps device
- * copies (replacing earlier ones); *pairs (may be NULL) = the included
- * (target cell, coarse cell) pairs. Synchronous. */
+ * copies (replacing earlier ones, after waiting for the device when there
+ * were any); *pairs (may be NULL) = the included (target cell, coarse cell)
+ * pairs. Synchronous; not to be called concurrently with other calls on the
+ * same plan from other threads. */
 int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, const int8_t* octant,
                            int64_t* pairs);
 
 /* Adds the coarse contributions into L[20][T*512]: com[3][S*512] (the fine
  * centres of the targets), Mp[20][Sp*512], comp[3][Sp*512] the coarse store
- * (e.g. from ot_fmm_m2m). One work-group per target that has substitutes. */
+ * (e.g. from ot_fmm_m2m); device pointers, 16-byte aligned, caller-owned.
+ * EINVAL: no tables set, a null or misaligned pointer, L overlapping an input
+ * (nothing enqueued). Enqueue only, on `stream`; targets without substitutes
+ * are left untouched. */
 int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp, double* L,
                        void* stream);
 

@@ -809,6 +809,17 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
         (void)hipFree(d_mask);
         return rc;
     }
+    if (plan->d_coarse) {
+        // earlier tables may still be read by a launch in flight
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipFree(d_tab);
+            (void)hipFree(d_list);
+            (void)hipFree(d_cell);
+            (void)hipFree(d_mask);
+            return hip_fail(e, "hipDeviceSynchronize");
+        }
+    }
     (void)hipFree(plan->d_lane_cell);
     (void)hipFree(plan->d_lane_mask);
     plan->d_lane_cell = d_cell;
