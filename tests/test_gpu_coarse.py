@@ -191,3 +191,23 @@ def test_set_coarse_rejects_bad_tables(ot):
                                  ctypes.c_void_p(L.data_ptr()), None)
     assert rc == ot.OT_FMM_EINVAL
     assert np.all(_host(big) == 0.0)
+
+
+def test_no_substitutes_leaves_L_untouched(ot):
+    """Tables without any substitute: zero pairs, nothing launched, L keeps
+    its values; replacing them with real tables afterwards works."""
+    batch, M, X, coarse, octant, Mp, Xp = _case(4, 87, 0.5, True)
+    plan = ot.Plan.from_batch(batch)
+    Sp = Mp.shape[1] // SUB3
+    none = np.full_like(coarse, -1)
+    assert plan.set_coarse(Sp, none, np.zeros_like(octant)) == 0
+    import torch
+    L = torch.full((20, batch["T"] * SUB3), 3.25, dtype=torch.float64, device="cuda")
+    dX, dMp, dXp = _dev(X), _dev(Mp), _dev(Xp)
+    plan.coarse_fine(dX, dMp, dXp, L)
+    assert np.all(_host(L) == 3.25)
+    plan.set_coarse(Sp, coarse, octant)
+    L.zero_()
+    plan.coarse_fine(dX, dMp, dXp, L)
+    ref, A = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, want_abs=True)
+    assert_parity(_host(L), ref, TOL, what="after replacing tables", A=A)
