@@ -18,52 +18,68 @@ struct CoarseParams {
     const double* mom_c;    // coarse moments [20][c_stride]
     const double* pos_c;    // coarse centres [3][c_stride]
     long c_stride;
-    const int* list;        // work list: target index, most work first
-    const int2* coarse;     // [T][27] {coarse node P, octant o}, P = -1: none
+    const int4* items;      // work items {target, lane order, first entry, entries}, most work first
+    const int4* entries;    // substituted slots {slot, coarse node P, octant o, 0}
+    const int* lane_cell;   // [orders][512] target cell of each lane
+    const unsigned long long* cell_mask;  // [27][512] bit J: coarse cell J included for cell c
     const int4* rel;        // forward relations (.z: packed periodic shift)
     const int* own_blk;     // target -> store block
-    const int* lane_cell;   // [27][512] target cell of each lane, per slot
-    const unsigned long long* lane_mask;  // [27][512] bit J: coarse cell J included
     double* out;            // L [20][out_stride], accumulated
     long out_stride;
     double period[3];
 };
 
-// One work-group (8 wavefronts) per target with substitutes. For each
-// substituted slot the 64 coarse cells of the octant are staged in LDS; lane
-// l then takes target cell lane_cell[slot][l] -- per slot the cells are
-// ordered by their number of included coarse cells, so that the lanes of a
-// wavefront run loops of similar length -- and walks the set bits of its
-// inclusion mask (every child j = 8 s + 2 J + {0,1}^3 of J satisfies
-// |j - i|^2 > 16 and the common parent criterion |J + 4 s - floor(i/2)|^2
-// <= 16 holds). The partial sums of a slot are added to the cell's
-// trace-reduced accumulators in LDS, one lane per cell and slot, slots in
-// order: deterministic. The last phase expands them and adds L.
-__global__ void __launch_bounds__(512) k_coarse_fine(const CoarseParams p)
+constexpr int kCoarseBatch = 8;  // substituted slots staged together
+
+// One work-group (8 wavefronts) per target with substitutes. The coarse
+// cells of up to 8 substituted slots are staged in LDS at once, value-major
+// (one row of 64 coarse cells per value; measured faster than a cell-major
+// layout read with 16-byte loads, which leaves room for 6 slots only). Lane l
+// takes target cell lane_cell[order][l]: per pattern of substituted slots the
+// cells are ordered by their total number of included coarse cells, so that
+// the lanes of a wavefront run loops of similar length. A lane walks, in one
+// loop over the batch, the set bits of its cell's inclusion mask of each
+// slot (every child j = 8 s + 2 J + {0,1}^3 of coarse cell J satisfies
+// |j - i|^2 > 16, and the common parent criterion |J + 4 s - floor(i/2)|^2
+// <= 16 holds), with its accumulators in registers; the order of the sums is
+// fixed (slots, then J ascending): deterministic. The accumulators go through
+// LDS at the end so that L is read and written in cell order. (The
+// wavefronts of a work-group are unevenly loaded -- the busiest cells share
+// wavefront 0 -- and splitting cells over lanes would need a second 64 KiB
+// of LDS for the partial sums; at 0.2% of a step this was left.)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_fine(const CoarseParams p)
 {
     constexpr int kNc = 3 + kNRed;                        // staged values per coarse cell
     constexpr int kNa = ModeTraits<MODE_FWD_STORE>::nacc;  // kept L_a of the reduced form
-    __shared__ double s_acc[kNa][kSub3];
-    __shared__ double s_src[kNc][64];  // value-major: lanes gather distinct J
+    constexpr int kSlotVals = kNc * 64;
+    __shared__ double s_src[kCoarseBatch * kSlotVals];
+    __shared__ int s_slot[kCoarseBatch];
+    static_assert(kNa * kSub3 <= kCoarseBatch * kSlotVals, "epilogue reuses the staging buffer");
     const int tid = threadIdx.x;
-    const int t = p.list[blockIdx.x];
-    const long own0 = (long)p.own_blk[t] * kSub3;
+    const int4 it = p.items[blockIdx.x];  // uniform
+    const int t = it.x;
+    const int cell = p.lane_cell[(long)it.y * kSub3 + tid];
+    const long own = (long)p.own_blk[t] * kSub3 + cell;
+    const double xi = p.pos[own], yi = p.pos[p.pos_stride + own], zi = p.pos[2 * p.pos_stride + own];
+    double acc[kNa];
 #pragma unroll
-    for (int a = 0; a < kNa; ++a) s_acc[a][tid] = 0.0;
+    for (int a = 0; a < kNa; ++a) acc[a] = 0.0;
 
-    for (int slot = 0; slot < 27; ++slot) {
-        const int2 cs = p.coarse[t * 27 + slot];  // uniform
-        if (cs.x < 0) continue;
-        const int o = cs.y;
-        const int packed = p.rel[t * 27 + slot].z;
-        __syncthreads();  // the previous slot's sources and accumulators are done
-        for (int v = tid; v < 64 * kNc; v += 512) {
-            const int k = v >> 6, J = v & 63;
+    for (int b0 = 0; b0 < it.w; b0 += kCoarseBatch) {
+        const int nb = (it.w - b0 < kCoarseBatch) ? it.w - b0 : kCoarseBatch;
+        const int4* ent = p.entries + it.z + b0;
+        __syncthreads();  // the previous batch is no longer read
+        for (int v = tid; v < nb * kSlotVals; v += 512) {
+            const int b = v / kSlotVals, r = v - b * kSlotVals;
+            const int k = r >> 6, J = r & 63;
+            const int4 e = ent[b];
+            const int o = e.z;
             const int cx = J & 3, cy = (J >> 2) & 3, cz = J >> 4;
             const int pc = (cx + 4 * (o & 1)) + 8 * (cy + 4 * ((o >> 1) & 1)) + 64 * (cz + 4 * (o >> 2));
-            const long jj = (long)cs.x * kSub3 + pc;
+            const long jj = (long)e.y * kSub3 + pc;
             double val;
             if (k < 3) {
+                const int packed = p.rel[(long)t * 27 + e.x].z;
                 const double sh = (double)(int)(int8_t)((packed >> (8 * k)) & 0xff) * p.period[k];
                 val = p.pos_c[k * p.c_stride + jj] + sh;
             } else {
@@ -71,35 +87,41 @@ __global__ void __launch_bounds__(512) k_coarse_fine(const CoarseParams p)
                 val = c_scale_fwd[cP] * p.mom_c[cP * p.c_stride + jj];
                 if (cS >= 0) val -= c_scale_fwd[cS] * p.mom_c[cS * p.c_stride + jj];
             }
-            s_src[k][J] = val;
+            s_src[v] = val;
         }
+        if (tid < nb) s_slot[tid] = ent[tid].x;
         __syncthreads();
-        unsigned long long mask = p.lane_mask[slot * kSub3 + tid];
-        if (mask) {
-            const int cell = p.lane_cell[slot * kSub3 + tid];
-            const long own = own0 + cell;
-            const double xi = p.pos[own], yi = p.pos[p.pos_stride + own], zi = p.pos[2 * p.pos_stride + own];
-            double acc[kNa];
+        // one loop over the lane's (slot, coarse cell) pairs of the batch, so
+        // that a wavefront runs as many trips as its busiest lane has pairs;
+        // the next slot's mask is loaded while the current one is worked on
+        int b = 0;
+        unsigned long long cur = p.cell_mask[s_slot[0] * kSub3 + cell];
+        unsigned long long nxt = nb > 1 ? p.cell_mask[s_slot[1] * kSub3 + cell] : 0ull;
+        for (;;) {
+            while (cur == 0ull && b + 1 < nb) {
+                ++b;
+                cur = nxt;
+                nxt = b + 1 < nb ? p.cell_mask[s_slot[b + 1] * kSub3 + cell] : 0ull;
+            }
+            if (cur == 0ull) break;
+            const int J = __builtin_ctzll(cur);
+            cur &= cur - 1;
+            const double* src = s_src + b * kSlotVals + J;
+            double f[kNc];
 #pragma unroll
-            for (int a = 0; a < kNa; ++a) acc[a] = 0.0;
-            do {
-                const int J = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                double f[kNc];
-#pragma unroll
-                for (int k = 0; k < kNc; ++k) f[k] = s_src[k][J];
-                double G[20];
-                green<3>(xi - f[0], yi - f[1], zi - f[2], G);
-                contract_red<0, TRUNC3>(acc, f + 3, G, std::make_integer_sequence<int, 20>{});
-            } while (mask);
-#pragma unroll
-            for (int a = 0; a < kNa; ++a) s_acc[a][cell] += acc[a];
+            for (int k = 0; k < kNc; ++k) f[k] = src[k * 64];
+            double G[20];
+            green<3>(xi - f[0], yi - f[1], zi - f[2], G);
+            contract_red<0, TRUNC3>(acc, f + 3, G, std::make_integer_sequence<int, 20>{});
         }
     }
+    // back to cell order through LDS
     __syncthreads();
-    double acc[kNa];
 #pragma unroll
-    for (int a = 0; a < kNa; ++a) acc[a] = s_acc[a][tid];
+    for (int a = 0; a < kNa; ++a) s_src[a * kSub3 + cell] = acc[a];
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < kNa; ++a) acc[a] = s_src[a * kSub3 + tid];
     double L[20];
     expand<0>(acc, L, std::make_integer_sequence<int, 20>{});
     const long ob = (long)t * kSub3 + tid;

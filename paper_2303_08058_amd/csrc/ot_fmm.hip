@@ -46,6 +46,7 @@
 #include <numeric>
 #include <string>
 #include <utility>
+#include <unordered_map>
 #include <vector>
 
 #include "ot_common.h"
@@ -167,10 +168,10 @@ struct ot_fmm_plan_s {
     std::vector<uint32_t> missing;  // [T] bit s: slot s has no fine neighbour
     int32_t Sp_coarse = 0;
     int n_coarse_targets = 0;
-    int2* d_coarse = nullptr;       // [T][27] {coarse node, octant}
-    int* d_coarse_list = nullptr;   // targets with substitutes, most work first
-    int* d_lane_cell = nullptr;     // [27][512] target cell of each lane, per slot
-    unsigned long long* d_lane_mask = nullptr;  // [27][512] included coarse cells
+    int4* d_cf_items = nullptr;     // {target, lane order, first entry, entries}, most work first
+    int4* d_cf_entries = nullptr;   // {slot, coarse node, octant, 0}
+    int* d_cf_cells = nullptr;      // [orders][512] target cell of each lane
+    unsigned long long* d_cf_mask = nullptr;  // [27][512] included coarse cells per target cell
 };
 
 namespace {
@@ -357,14 +358,14 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_fwd_local);
     (void)hipFree(p->d_rev_local);
     (void)hipFree(p->d_counters);
-    (void)hipFree(p->d_coarse);
-    (void)hipFree(p->d_coarse_list);
-    (void)hipFree(p->d_lane_cell);
-    (void)hipFree(p->d_lane_mask);
-    p->d_coarse = nullptr;
-    p->d_coarse_list = nullptr;
-    p->d_lane_cell = nullptr;
-    p->d_lane_mask = nullptr;
+    (void)hipFree(p->d_cf_items);
+    (void)hipFree(p->d_cf_entries);
+    (void)hipFree(p->d_cf_cells);
+    (void)hipFree(p->d_cf_mask);
+    p->d_cf_items = nullptr;
+    p->d_cf_entries = nullptr;
+    p->d_cf_cells = nullptr;
+    p->d_cf_mask = nullptr;
 }
 
 // Work order: longest work first (a greedy longest-processing-time list for
@@ -739,8 +740,6 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
     if (Sp <= 0 || !coarse || !octant) return fail(OT_FMM_EINVAL, "Sp > 0, coarse and octant required");
     if ((int64_t)Sp * kSub3 * 20 > ((int64_t)1 << 40)) return fail(OT_FMM_EINVAL, "coarse store too large");
     const int T = plan->T;
-    std::vector<int2> tab((size_t)T * 27);
-    std::vector<int> count(T, 0);
     for (int t = 0; t < T; ++t)
         for (int q = 0; q < 27; ++q) {
             const int32_t c = coarse[(int64_t)t * 27 + q];
@@ -749,19 +748,14 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
             if (c >= 0 && !((plan->missing[t] >> q) & 1u))
                 return fail(OT_FMM_EINVAL, "a substitute is given for a neighbour that is present");
             if (c >= 0 && (o < 0 || o > 7)) return fail(OT_FMM_EINVAL, "octant out of range");
-            tab[(size_t)t * 27 + q] = make_int2(c, c >= 0 ? o : 0);
-            count[t] += c >= 0;
         }
     // per slot (geometry only): the coarse cells included for each target
-    // cell as a 64-bit mask, the cells in lane order (most included first),
-    // the included pairs and the loop trips of the 8 wavefronts
-    std::vector<unsigned long long> lane_mask((size_t)27 * kSub3);
-    std::vector<int> lane_cell((size_t)27 * kSub3);
-    int64_t slot_pairs[27] = {0}, slot_cost[27] = {0};
+    // cell, as a 64-bit mask, and their number
+    std::vector<unsigned long long> mask((size_t)27 * kSub3, 0ull);
+    std::vector<int> cnt((size_t)27 * kSub3, 0);
+    int64_t slot_pairs[27] = {0};
     for (int q = 0; q < 27; ++q) {
         const int so[3] = {q % 3, (q / 3) % 3, q / 9};
-        std::vector<unsigned long long> m(kSub3, 0ull);
-        std::vector<int> cnt(kSub3, 0), order(kSub3);
         for (int c = 0; c < kSub3; ++c) {
             const int hi[3] = {8 + c % 8, 8 + (c / 8) % 8, 8 + c / 64};
             for (int J = 0; J < 64; ++J) {
@@ -771,65 +765,95 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
                     all_in = criterion(hi[0], hi[1], hi[2], 8 * so[0] + 2 * cj[0] + (n & 1),
                                        8 * so[1] + 2 * cj[1] + ((n >> 1) & 1), 8 * so[2] + 2 * cj[2] + (n >> 2));
                 if (all_in) {
-                    m[c] |= 1ull << J;
-                    ++cnt[c];
+                    mask[(size_t)q * kSub3 + c] |= 1ull << J;
+                    ++cnt[(size_t)q * kSub3 + c];
                 }
             }
-            slot_pairs[q] += cnt[c];
-            order[c] = c;
+            slot_pairs[q] += cnt[(size_t)q * kSub3 + c];
         }
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
-        for (int l = 0; l < kSub3; ++l) {
-            lane_cell[(size_t)q * kSub3 + l] = order[l];
-            lane_mask[(size_t)q * kSub3 + l] = m[order[l]];
-        }
-        for (int w = 0; w < kSub3 / 64; ++w) slot_cost[q] += cnt[order[64 * w]];
     }
+    // per pattern of substituted slots: the target cells in lane order, by
+    // decreasing total count, and the summed loop trips of the 8 wavefronts
+    std::unordered_map<uint32_t, int> pattern_id;
+    std::vector<int> cells;
+    std::vector<int64_t> pattern_cost;
+    std::vector<int4> items, entries;
+    std::vector<int64_t> item_cost;
     int64_t total = 0;
-    std::vector<int> list;
-    std::vector<int64_t> cost(T, 0);
     for (int t = 0; t < T; ++t) {
-        if (count[t]) list.push_back(t);
-        for (int q = 0; q < 27; ++q)
-            if (tab[(size_t)t * 27 + q].x >= 0) {
-                total += slot_pairs[q];
-                cost[t] += slot_cost[q] + 4;  // + staging
-            }
+        uint32_t pat = 0;
+        const int first = (int)entries.size();
+        for (int q = 0; q < 27; ++q) {
+            const int32_t c = coarse[(int64_t)t * 27 + q];
+            if (c < 0) continue;
+            pat |= 1u << q;
+            entries.push_back(make_int4(q, c, octant[(int64_t)t * 27 + q], 0));
+            total += slot_pairs[q];
+        }
+        if (!pat) continue;
+        auto f = pattern_id.find(pat);
+        int id;
+        if (f == pattern_id.end()) {
+            id = (int)pattern_cost.size();
+            pattern_id.emplace(pat, id);
+            std::vector<int> tot(kSub3, 0), order(kSub3);
+            for (int q = 0; q < 27; ++q)
+                if ((pat >> q) & 1u)
+                    for (int c = 0; c < kSub3; ++c) tot[c] += cnt[(size_t)q * kSub3 + c];
+            for (int c = 0; c < kSub3; ++c) order[c] = c;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tot[x] > tot[y]; });
+            cells.insert(cells.end(), order.begin(), order.end());
+            int64_t cost = 0;
+            for (int w = 0; w < kSub3 / 64; ++w) cost += tot[order[64 * w]];
+            pattern_cost.push_back(cost);
+        } else {
+            id = f->second;
+        }
+        const int n = (int)entries.size() - first;
+        items.push_back(make_int4(t, id, first, n));
+        item_cost.push_back(pattern_cost[id] + 8 * n);  // + staging
     }
-    std::stable_sort(list.begin(), list.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    int2* d_tab = nullptr;
-    int* d_list = nullptr;
-    int* d_cell = nullptr;
+    std::vector<int> idx(items.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return item_cost[x] > item_cost[y]; });
+    std::vector<int4> sorted(items.size());
+    for (size_t i = 0; i < idx.size(); ++i) sorted[i] = items[idx[i]];
+    if (entries.empty()) entries.push_back(make_int4(0, 0, 0, 0));  // keep every table non-empty
+    if (sorted.empty()) sorted.push_back(make_int4(0, 0, 0, 0));
+    if (cells.empty()) cells.assign(kSub3, 0);
+    int4* d_items = nullptr;
+    int4* d_entries = nullptr;
+    int* d_cells = nullptr;
     unsigned long long* d_mask = nullptr;
-    if ((rc = upload(&d_tab, tab)) || (rc = upload(&d_list, list)) || (rc = upload(&d_cell, lane_cell)) ||
-        (rc = upload(&d_mask, lane_mask))) {
-        (void)hipFree(d_tab);
-        (void)hipFree(d_list);
-        (void)hipFree(d_cell);
+    if ((rc = upload(&d_items, sorted)) || (rc = upload(&d_entries, entries)) || (rc = upload(&d_cells, cells)) ||
+        (rc = upload(&d_mask, mask))) {
+        (void)hipFree(d_items);
+        (void)hipFree(d_entries);
+        (void)hipFree(d_cells);
         (void)hipFree(d_mask);
         return rc;
     }
-    if (plan->d_coarse) {
+    if (plan->d_cf_items) {
         // earlier tables may still be read by a launch in flight
         hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) {
-            (void)hipFree(d_tab);
-            (void)hipFree(d_list);
-            (void)hipFree(d_cell);
+            (void)hipFree(d_items);
+            (void)hipFree(d_entries);
+            (void)hipFree(d_cells);
             (void)hipFree(d_mask);
             return hip_fail(e, "hipDeviceSynchronize");
         }
     }
-    (void)hipFree(plan->d_lane_cell);
-    (void)hipFree(plan->d_lane_mask);
-    plan->d_lane_cell = d_cell;
-    plan->d_lane_mask = d_mask;
-    (void)hipFree(plan->d_coarse);
-    (void)hipFree(plan->d_coarse_list);
-    plan->d_coarse = d_tab;
-    plan->d_coarse_list = d_list;
+    (void)hipFree(plan->d_cf_items);
+    (void)hipFree(plan->d_cf_entries);
+    (void)hipFree(plan->d_cf_cells);
+    (void)hipFree(plan->d_cf_mask);
+    plan->d_cf_items = d_items;
+    plan->d_cf_entries = d_entries;
+    plan->d_cf_cells = d_cells;
+    plan->d_cf_mask = d_mask;
     plan->Sp_coarse = Sp;
-    plan->n_coarse_targets = (int)list.size();
+    plan->n_coarse_targets = (int)items.size();
     if (pairs) *pairs = total;
     return OT_FMM_OK;
 }
@@ -854,12 +878,12 @@ int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, co
     cp.mom_c = Mp;
     cp.pos_c = comp;
     cp.c_stride = NP;
-    cp.list = plan->d_coarse_list;
-    cp.coarse = plan->d_coarse;
+    cp.items = plan->d_cf_items;
+    cp.entries = plan->d_cf_entries;
     cp.rel = plan->d_fwd_rel;
     cp.own_blk = plan->d_tgt;
-    cp.lane_cell = plan->d_lane_cell;
-    cp.lane_mask = plan->d_lane_mask;
+    cp.lane_cell = plan->d_cf_cells;
+    cp.cell_mask = plan->d_cf_mask;
     cp.out = L;
     cp.out_stride = NT;
     for (int k = 0; k < 3; ++k) cp.period[k] = plan->period[k];
