@@ -27,6 +27,9 @@ def test_slot_pair_counts_follow_the_criterion():
     and corner blocks of a full sub-grid's 921,088 pairs, equal to the
     library's own stencil tables (an independent count) and, for one target
     cell per slot, to a brute-force count with the oracle's criterion."""
+    lib = os.path.join(ROOT, "paper_2303_08058_amd", "libotfmm.so")
+    if not os.path.exists(lib):
+        subprocess.check_call([sys.executable, os.path.join(ROOT, "paper_2303_08058_amd", "build.py")])
     import paper_2303_08058_amd as ot
     sp = np.array(bench._slot_pairs(np))
     assert sp.sum() == 921088
