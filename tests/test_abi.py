@@ -73,7 +73,8 @@ def _good():
 
 
 @pytest.mark.parametrize("case", ["S0", "T0", "tgt_range", "tgt_dup", "nbr_range", "self_slot",
-                                  "shift_no_period", "conflict"])
+                                  "shift_no_period", "conflict", "too_large", "shift_minus128",
+                                  "period_nan"])
 def test_plan_create_rejects_bad_descriptors(lib, case):
     S, T, tgt, nbr = _good()
     shift, period = None, None
@@ -98,6 +99,15 @@ def test_plan_create_rejects_bad_descriptors(lib, case):
         nbr[1, 12] = -1
         S, T, tgt = 3, 2, np.array([0, 2])
         nbr[1, 13] = 2
+    elif case == "too_large":
+        S = 1 << 27                      # 20 x 512 x S doubles exceed 2^40
+    elif case == "shift_minus128":
+        shift = np.zeros((2, 27, 3))
+        shift[0, 14, 0] = -128           # its negation does not fit the reverse table
+        period = np.ones(3)
+    elif case == "period_nan":
+        shift = np.zeros((2, 27, 3))
+        period = np.array([1.0, np.nan, 1.0])
     rc, h = _plan_create(lib, S, T, tgt, nbr, shift, period)
     assert rc == -1
 
