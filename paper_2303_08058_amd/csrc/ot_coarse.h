@@ -1,12 +1,11 @@
 // ot_coarse.h -- device side of the coarse substitute for missing neighbours
 // (Sec. 2.1 names the octree FMM without formulas; this is a reading of the
 // interaction across a refinement boundary): for a target whose fine
-// neighbour in slot s is missing and is
-// covered by octant o of a parent-level node P, each of the 4^3 coarse cells
-// J of that octant stands in for its 2x2x2 fine children when all of them
-// would be in the target cell's stencil. Included by ot_fmm.hip after
-// ot_interact.h (uses its derivatives, trace-reduced contraction and staging
-// scales).
+// neighbour in slot s is missing and is covered by octant o of a
+// parent-level node P, each of the 4^3 coarse cells J of that octant stands
+// in for its 2x2x2 fine children when all of them would be in the target
+// cell's stencil. Included by ot_fmm.hip after ot_interact.h (uses its
+// derivatives, trace-reduced contraction and staging scales).
 #pragma once
 
 #include "ot_interact.h"
