@@ -202,6 +202,12 @@ def main():
         tree = tree_passes(args.n, args.tree_steps, Md, Xd, L, ot, synthetic, np, torch, dev,
                            plan=plan, batch=batch)
 
+    # ------------------------------------------------- a two-level FMM step
+    two_level = None
+    if args.tree_steps > 0 and args.n % 2 == 0:
+        two_level = two_level_step(args.n, args.tree_steps, plan, batch, fs, Md, Xd, L, ot, synthetic,
+                                   np, torch, dev)
+
     # --------------------------------------- batched vs per-sub-grid launches
     per_sub = None
     if args.per_subgrid_n > 0:
@@ -251,6 +257,7 @@ def main():
         "fwd_pairs_per_s": fwd_pairs_s,
         "direct_launch_ms_per_step": round(sum_ms, 3),
         "tree_passes": tree,
+        "two_level_step": two_level,
         "batched_vs_per_subgrid": per_sub,
         "cpu_baseline": cpu,
     }
@@ -353,6 +360,57 @@ def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev, plan=None, b
     log("copy 2 GiB      %.3f ms  %.0f GB/s" % (ms, out["copy_2GiB"]["gbs"]))
     del a, b
     return out
+
+
+def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torch, dev):
+    """A two-level step on the benchmark store, from the library's calls in
+    sequence on one stream: upward pass to the (n/2)^3 parent level, fine
+    interaction plus coarse substitutes for the missing neighbours, the
+    parent level's interaction, downward pass into the fine coefficients,
+    evaluation of force and energy. HIP events around the whole sequence."""
+    ch = synthetic.octree_children(n)
+    Sp, S = ch.shape[0], n ** 3
+    tree = ot.Tree(ch, S)
+    parent = synthetic.parent_lattice(n, periodic=batch.get("period") is not None)
+    pplan = ot.Plan.from_batch(parent)
+    coarse, octant = synthetic.coarse_tables(n, batch)
+    cpairs = plan.set_coarse(Sp, coarse, octant)
+    f64 = dict(dtype=torch.float64, device=dev)
+    Mp = torch.empty((20, Sp * 512), **f64)
+    Xp = torch.empty((3, Sp * 512), **f64)
+    Lp = torch.empty((20, Sp * 512), **f64)
+    F = torch.empty((3, S * 512), **f64)
+    W = torch.empty((S * 512,), **f64)
+
+    def step():
+        tree.m2m(Md, Xd, Mp, Xp)
+        plan.multipole_batched(Md, Xd, L, sched=fs)
+        plan.coarse_fine(Xd, Mp, Xp, L)
+        pplan.multipole_batched(Mp, Xp, Lp)
+        tree.l2l(Lp, Xp, Xd, L)
+        ot.ot_fmm_evaluate(Md, L, F, W)
+
+    step()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fine_pairs, parent_pairs = plan.pairs(), pplan.pairs()
+    total = fine_pairs + cpairs + parent_pairs
+    log("two-level step %.2f ms: %d fine + %d coarse + %d parent-level pairs" % (
+        ms, fine_pairs, cpairs, parent_pairs))
+    tree.close()
+    pplan.close()
+    return {"mean_ms": round(ms, 3), "fine_pairs": fine_pairs, "coarse_pairs": cpairs,
+            "parent_pairs": parent_pairs, "pairs_per_s": total / (ms * 1e-3),
+            "passes": ["m2m", "forward (fine)", "coarse_fine", "forward (parent level)", "l2l",
+                       "evaluate"]}
 
 
 def per_subgrid_comparison(n, ot, synthetic, np, torch, dev):

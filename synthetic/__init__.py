@@ -228,6 +228,18 @@ def octree_children(n):
     return (c[..., 0] + n * c[..., 1] + n * n * c[..., 2]).astype(np.int32)
 
 
+def parent_lattice(n, periodic=True):
+    """The (n/2)^3 parent level of an n^3 lattice store as a batch of its own
+    (all parent nodes are targets, numbered like octree_children(n)). Centres
+    stay in fine-cell units, so the periodic image shift is the fine domain
+    length: twice what lattice_batch(n/2) assumes for cells of unit size."""
+    assert n % 2 == 0
+    b = lattice_batch(n // 2, periodic=periodic)
+    if periodic:
+        b["period"] = 2.0 * b["period"]
+    return b
+
+
 def coarse_tables(n, batch):
     """Coarse substitutes of the missing neighbours of a lattice batch over an
     n^3 store (n even) whose parent level is octree_children(n): for each

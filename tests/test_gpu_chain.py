@@ -38,17 +38,18 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def test_two_level_step_matches_the_oracle_chain():
+@pytest.mark.parametrize("periodic", [False, True])
+def test_two_level_step_matches_the_oracle_chain(periodic):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2303_08058_amd as ot
 
     n = 4
-    fine, M, X = synthetic.batched_config(n, 91, missing_frac=0.5, periodic=False)
+    fine, M, X = synthetic.batched_config(n, 91, missing_frac=0.5, periodic=periodic)
     coarse, octant = synthetic.coarse_tables(n, fine)
     children = synthetic.octree_children(n)
     Sp = children.shape[0]
-    parent = synthetic.lattice_batch(n // 2, periodic=False)
+    parent = synthetic.parent_lattice(n, periodic=periodic)
     assert (coarse >= 0).sum() > 10
 
     # oracle chain

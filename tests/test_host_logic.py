@@ -148,3 +148,24 @@ def test_xcd_local_orders(periodic):
     _, work, _ = ot.ot_fmm_count_pairs(batch)
     per = np.bincount(np.argsort(fl) % 8, weights=work, minlength=8)
     assert per.max() / per.min() < 1.05
+
+
+def test_parent_lattice_keeps_the_fine_domain_length():
+    """The parent level's periodic shift is the fine domain's length (centres
+    stay in fine-cell units), and its node numbering is the octree's."""
+    import synthetic
+    for n in (4, 8):
+        fine = synthetic.lattice_batch(n, periodic=True)
+        par = synthetic.parent_lattice(n, periodic=True)
+        assert np.array_equal(par["period"], fine["period"])
+        ch = synthetic.octree_children(n)
+        assert par["S"] == ch.shape[0] == (n // 2) ** 3
+        # parent node P covers fine sub-grids 2p + {0,1} per axis
+        m = n // 2
+        for P in (0, m * m * m - 1, 1 + m):
+            px, py, pz = P % m, (P // m) % m, P // (m * m)
+            kids = sorted(int(c) for c in ch[P])
+            want = sorted((2 * px + a) + n * (2 * py + b) + n * n * (2 * pz + c)
+                          for c in (0, 1) for b in (0, 1) for a in (0, 1))
+            assert kids == want
+    assert synthetic.parent_lattice(4, periodic=False)["period"] is None
