@@ -55,10 +55,14 @@ def _load():
     lib.orc_in_stencil.argtypes = [P, P]
     lib.orc_in_stencil.restype = i
     lib.orc_max_threads.restype = i
-    lib.orc_block_forward.argtypes = [P, i, P, i, P, P, i]
-    lib.orc_block_forward.restype = i
-    lib.orc_batched_forward.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
-    lib.orc_batched_forward.restype = i
+    lib.orc_green_general.argtypes = [P, i, P]
+    lib.orc_green_general.restype = i
+    for f in (lib.orc_block_forward, lib.orc_block_forward_full):
+        f.argtypes = [P, i, P, i, P, P, i]
+        f.restype = i
+    for f in (lib.orc_batched_forward, lib.orc_batched_forward_full):
+        f.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
+        f.restype = i
     lib.orc_batched_forward_cs.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
     lib.orc_batched_forward_cs.restype = i
     lib.orc_batched_backward.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
@@ -106,21 +110,34 @@ def green(r, order: int = 4) -> np.ndarray:
     return out
 
 
+def green_general(r, order: int = 6) -> np.ndarray:
+    """d^gamma(-1/|r|) for |gamma| <= order (<= 6) from the general closed form
+    (Hobson's formula), graded-lex order."""
+    n = (order + 1) * (order + 2) * (order + 3) // 6
+    r = _f64(r)
+    out = np.zeros(n, np.float64)
+    if _load().orc_green_general(_ptr(r), order, _ptr(out)):
+        raise ValueError("order must be in 0..6")
+    return out
+
+
 def in_stencil(hi, hj) -> bool:
     a = _i32(hi)
     b = _i32(hj)
     return bool(_load().orc_in_stencil(_ptr(a), _ptr(b)))
 
 
-def block_forward(M, X, mmax: int = 3, want_abs: bool = False, nthreads: int = 0):
+def block_forward(M, X, mmax: int = 3, want_abs: bool = False, nthreads: int = 0,
+                  full: bool = False):
     """Single 24^3 halo block. M: (nm, 13824) with nm in {1, 20}; X: (3, 13824).
-    Returns L (20, 512) [and A (20, 512), the sum of term magnitudes]."""
+    Returns L (20, 512) [and A (20, 512), the sum of term magnitudes].
+    full=True: every output keeps every moment up to mmax (full truncation)."""
     M = _f64(M).reshape(-1, HALO3)
     X = _f64(X).reshape(3, HALO3)
     L = np.zeros((NM, SUB3), np.float64)
     A = np.zeros((NM, SUB3), np.float64) if want_abs else None
-    rc = _load().orc_block_forward(_ptr(M), M.shape[0], _ptr(X), mmax, _ptr(L), _ptr(A),
-                                   nthreads)
+    fn = _load().orc_block_forward_full if full else _load().orc_block_forward
+    rc = fn(_ptr(M), M.shape[0], _ptr(X), mmax, _ptr(L), _ptr(A), nthreads)
     if rc:
         raise ValueError("orc_block_forward rejected its arguments")
     return (L, A) if want_abs else L
@@ -136,8 +153,10 @@ def _batch_args(batch):
     return int(batch["S"]), int(batch["T"]), tgt, nbr, shift, period
 
 
-def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0):
-    """Batched forward over a selection of targets. Returns L (20, nsel*512)."""
+def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0,
+                    full: bool = False):
+    """Batched forward over a selection of targets. Returns L (20, nsel*512).
+    full=True: the full truncation (every output keeps every moment)."""
     S, T, tgt, nbr, shift, period = _batch_args(batch)
     tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
     M = _f64(M)
@@ -145,9 +164,9 @@ def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: in
     assert M.shape == (NM, S * SUB3) and X.shape == (3, S * SUB3)
     L = np.zeros((NM, len(tsel) * SUB3), np.float64)
     A = np.zeros_like(L) if want_abs else None
-    rc = _load().orc_batched_forward(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period),
-                                     _ptr(M), _ptr(X), _ptr(tsel), len(tsel), _ptr(L),
-                                     _ptr(A), nthreads)
+    fn = _load().orc_batched_forward_full if full else _load().orc_batched_forward
+    rc = fn(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M), _ptr(X), _ptr(tsel),
+            len(tsel), _ptr(L), _ptr(A), nthreads)
     if rc:
         raise ValueError("orc_batched_forward rejected its arguments")
     return (L, A) if want_abs else L

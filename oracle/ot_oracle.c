@@ -28,6 +28,10 @@
  * Component order of every 20- or 35-vector: graded lexicographic with x most
  * significant (1; x,y,z; xx,xy,xz,yy,yz,zz; xxx,xxy,...,zzz; xxxx,...).
  *
+ * A second truncation is available beside it (the "full" one: every output
+ * order keeps every moment |beta| <= 3, derivatives to order 6), with the
+ * derivatives from the general closed form of d^gamma(1/r).
+ *
  * Pins (tests/test_oracle_*.py): closed forms of G against symbolic
  * differentiation, Laplace trace identities, the lattice-point count of the
  * stencil, single-source closed forms, direct summation over point masses
@@ -174,6 +178,110 @@ static void local_coords(int c, int l[3])
 #undef FN
 #undef cabs_generic
 
+/* ---------------------------------------------------------------------------
+ * "Full" truncation, the variant beside the total-order one: every output
+ * order |alpha| <= 3 keeps every source moment |beta| <= 3, so derivatives of
+ * G are needed to order 6:
+ *   L_alpha(i) = sum_{j in S(i)} sum_{|beta| <= 3} s_beta M_beta(j) G_{alpha+beta}(X_i - X_j)
+ * Derivatives of any order come from the general closed form of d^gamma (1/r)
+ * (Hobson's formula), independent of the Kronecker-delta forms above: for
+ * gamma = (a, b, c), n = a + b + c,
+ *   d^gamma (1/r) = sum_{i <= a/2, j <= b/2, k <= c/2}
+ *       (-1)^(n-m) (2n-2m-1)!! r^-(2n-2m+1) h(a,i) h(b,j) h(c,k) x^(a-2i) y^(b-2j) z^(c-2k),
+ *   m = i + j + k,  h(a,i) = a! / (2^i i! (a-2i)!),  (-1)!! = 1,
+ * and G_gamma = -d^gamma (1/r).
+ * ------------------------------------------------------------------------- */
+#define NG6 84 /* derivatives up to order 6 */
+static int g6_exp[NG6][3];
+static int g6_sum[NM][NM]; /* index of alpha + beta among the NG6 */
+static int g6_ready = 0;
+
+static void init_tables6(void)
+{
+    if (g6_ready) return;
+    init_tables();
+    int k = 0;
+    for (int n = 0; n <= 6; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                g6_exp[k][0] = a;
+                g6_exp[k][1] = b;
+                g6_exp[k][2] = n - a - b;
+                ++k;
+            }
+    for (int g = 0; g < NM; ++g)
+        for (int h = 0; h < NM; ++h) {
+            int e[3] = {g_exp[g][0] + g_exp[h][0], g_exp[g][1] + g_exp[h][1], g_exp[g][2] + g_exp[h][2]};
+            g6_sum[g][h] = -1;
+            for (int q = 0; q < NG6; ++q)
+                if (g6_exp[q][0] == e[0] && g6_exp[q][1] == e[1] && g6_exp[q][2] == e[2]) g6_sum[g][h] = q;
+        }
+    g6_ready = 1;
+}
+
+static double double_factorial(int n)
+{
+    double f = 1.0;
+    for (int k = n; k > 1; k -= 2) f *= k;
+    return f;
+}
+
+static double hobson_h(int a, int i) { return factorial(a) / (ldexp(1.0, i) * factorial(i) * factorial(a - 2 * i)); }
+
+static void green_general(const double r[3], int order, double *G)
+{
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rinv = 1.0 / sqrt(r2);
+    double pw[3][7];
+    for (int d = 0; d < 3; ++d) {
+        pw[d][0] = 1.0;
+        for (int p = 1; p <= 6; ++p) pw[d][p] = pw[d][p - 1] * r[d];
+    }
+    double rp[14]; /* rinv^q */
+    rp[0] = 1.0;
+    for (int q = 1; q < 14; ++q) rp[q] = rp[q - 1] * rinv;
+    int n_out = ncomp(order);
+    for (int g = 0; g < n_out; ++g) {
+        int a = g6_exp[g][0], b = g6_exp[g][1], c = g6_exp[g][2];
+        int n = a + b + c;
+        double v = 0.0;
+        for (int i = 0; 2 * i <= a; ++i)
+            for (int j = 0; 2 * j <= b; ++j)
+                for (int k = 0; 2 * k <= c; ++k) {
+                    int m = i + j + k;
+                    double coef = (((n - m) & 1) ? -1.0 : 1.0) * double_factorial(2 * n - 2 * m - 1) *
+                                  hobson_h(a, i) * hobson_h(b, j) * hobson_h(c, k);
+                    v += coef * rp[2 * n - 2 * m + 1] * pw[0][a - 2 * i] * pw[1][b - 2 * j] * pw[2][c - 2 * k];
+                }
+        G[g] = -v;
+    }
+}
+
+/* One pair, full truncation (moments up to order mmax for every output). */
+static void pair_forward_full(const double Xi[3], const double Xj[3], const double *Mj, int nm, int mmax,
+                              double *L, double *Aabs)
+{
+    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
+    double G[NG6];
+    green_general(r, 6, G);
+    for (int a = 0; a < NM; ++a)
+        for (int b = 0; b < nm; ++b) {
+            if (order_of(b) > mmax) continue;
+            double term = taylor_sign(b) * Mj[b] * G[g6_sum[a][b]];
+            L[a] += term;
+            if (Aabs) Aabs[a] += fabs(term);
+        }
+}
+
+static void pair_forward_any(int full, const double Xi[3], const double Xj[3], const double *Mj, int nm,
+                             int mmax, double *L, double *Aabs)
+{
+    if (full)
+        pair_forward_full(Xi, Xj, Mj, nm, mmax, L, Aabs);
+    else
+        pair_forward_re(Xi, Xj, Mj, nm, mmax, L, Aabs);
+}
+
 /* nthreads > 0: that many threads for this call; 0: the process default
  * (OMP_NUM_THREADS or all cores), also after a call that asked for fewer. */
 static int g_default_threads = 0;
@@ -207,6 +315,15 @@ void orc_green(const double r[3], int order, double *G)
 
 int orc_in_stencil(const int hi[3], const int hj[3]) { return in_stencil(hi, hj); }
 
+/* G_gamma for |gamma| <= order (order <= 6) from the general closed form. */
+int orc_green_general(const double r[3], int order, double *G)
+{
+    if (order < 0 || order > 6) return -1;
+    init_tables6();
+    green_general(r, order, G);
+    return 0;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP
@@ -222,10 +339,11 @@ int orc_max_threads(void)
  * order 3), X[3][13824] centres of mass; L[20][512] for the central 8^3
  * (index x + 8 y + 64 z). All halo cells are available.
  * ------------------------------------------------------------------------- */
-int orc_block_forward(const double *M, int nm, const double *X, int mmax, double *L,
-                      double *Aabs, int nthreads)
+static int block_forward(int full, const double *M, int nm, const double *X, int mmax, double *L,
+                         double *Aabs, int nthreads)
 {
     init_tables();
+    init_tables6();
     if (nm != 1 && nm != NM) return -1;
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic)
@@ -246,7 +364,7 @@ int orc_block_forward(const double *M, int nm, const double *X, int mmax, double
                     double Xj[3] = {X[jidx], X[HALO3 + jidx], X[2 * HALO3 + jidx]};
                     double Mj[NM];
                     for (int b = 0; b < nm; ++b) Mj[b] = M[(size_t)b * HALO3 + jidx];
-                    pair_forward_re(Xi, Xj, Mj, nm, mmax, acc, Aabs ? aabs : NULL);
+                    pair_forward_any(full, Xi, Xj, Mj, nm, mmax, acc, Aabs ? aabs : NULL);
                 }
         for (int a = 0; a < NM; ++a) {
             L[a * SUB3 + ci] = acc[a];
@@ -287,12 +405,13 @@ static void neighbour_shift(const int8_t *shift, const double *period, int t, in
                                   : 0.0;
 }
 
-int orc_batched_forward(int S, int T, const int32_t *tgt, const int32_t *nbr,
-                        const int8_t *shift, const double *period, const double *M,
-                        const double *X, const int32_t *tsel, int nsel, double *L,
-                        double *Aabs, int nthreads)
+static int batched_forward(int full, int S, int T, const int32_t *tgt, const int32_t *nbr,
+                           const int8_t *shift, const double *period, const double *M,
+                           const double *X, const int32_t *tsel, int nsel, double *L,
+                           double *Aabs, int nthreads)
 {
     init_tables();
+    init_tables6();
     if (check_batch(S, T, tgt, nbr)) return -1;
     for (int q = 0; q < nsel; ++q)
         if (tsel[q] < 0 || tsel[q] >= T) return -1;
@@ -326,7 +445,7 @@ int orc_batched_forward(int S, int T, const int32_t *tgt, const int32_t *nbr,
                                     X[2 * NS + jidx] + sh[2]};
                     double Mj[NM];
                     for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
-                    pair_forward_re(Xi, Xj, Mj, NM, 3, acc, Aabs ? aabs : NULL);
+                    pair_forward_any(full, Xi, Xj, Mj, NM, 3, acc, Aabs ? aabs : NULL);
                 }
             }
             for (int a = 0; a < NM; ++a) {
@@ -335,6 +454,34 @@ int orc_batched_forward(int S, int T, const int32_t *tgt, const int32_t *nbr,
             }
         }
     return 0;
+}
+
+int orc_block_forward(const double *M, int nm, const double *X, int mmax, double *L,
+                      double *Aabs, int nthreads)
+{
+    return block_forward(0, M, nm, X, mmax, L, Aabs, nthreads);
+}
+
+int orc_block_forward_full(const double *M, int nm, const double *X, int mmax, double *L,
+                           double *Aabs, int nthreads)
+{
+    return block_forward(1, M, nm, X, mmax, L, Aabs, nthreads);
+}
+
+int orc_batched_forward(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                        const int8_t *shift, const double *period, const double *M,
+                        const double *X, const int32_t *tsel, int nsel, double *L,
+                        double *Aabs, int nthreads)
+{
+    return batched_forward(0, S, T, tgt, nbr, shift, period, M, X, tsel, nsel, L, Aabs, nthreads);
+}
+
+int orc_batched_forward_full(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                             const int8_t *shift, const double *period, const double *M,
+                             const double *X, const int32_t *tsel, int nsel, double *L,
+                             double *Aabs, int nthreads)
+{
+    return batched_forward(1, S, T, tgt, nbr, shift, period, M, X, tsel, nsel, L, Aabs, nthreads);
 }
 
 /* Coarse substitute for missing neighbours -- a reading: the paper gives no

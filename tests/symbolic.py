@@ -14,11 +14,11 @@ EXP3 = EXP4[:20]
 
 
 @functools.lru_cache(maxsize=None)
-def _derivative_functions():
+def _derivative_functions(maxorder=4):
     x, y, z = sp.symbols("x y z", real=True)
     G = -1 / sp.sqrt(x ** 2 + y ** 2 + z ** 2)
     fns = []
-    for a, b, c in EXP4:
+    for a, b, c in moment_exponents(maxorder):
         d = G
         if a:
             d = sp.diff(d, x, a)
@@ -35,4 +35,4 @@ def green_mp(r, order=4, dps=30):
     n = (order + 1) * (order + 2) * (order + 3) // 6
     with mpmath.workdps(dps):
         rx, ry, rz = (mpmath.mpf(float(v)) for v in r)
-        return [f(rx, ry, rz) for f in _derivative_functions()[:n]]
+        return [f(rx, ry, rz) for f in _derivative_functions(max(4, order))[:n]]

@@ -1,0 +1,189 @@
+"""Pins of the oracle's full truncation (every output order |alpha| <= 3 keeps
+every source moment |beta| <= 3, so derivatives of G to order 6), against
+facts fixed by mathematics and independent of its code: symbolic
+derivatives to order 6 (sympy, 30 digits), the order <= 4 closed forms
+written with Kronecker deltas, Laplace's equation for the derivatives and
+the outputs, mass-only sources (where both truncations coincide), the
+batched form against the single-block form on the gathered halo, and direct
+summation over point masses, whose error must now fall like a^4 for every
+output order (the total-order truncation: like a^(4-n)). CPU only.
+
+Planted mistakes each fail one of these: a wrong sign or double factorial
+in the general closed form (symbolic), a dropped Hobson term (symbolic,
+harmonic), a truncation still at |alpha| + |beta| <= 3 (direct summation),
+a wrong multi-index sum table (symbolic via the single-source closed form)."""
+import itertools
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import oracle  # noqa: E402
+import synthetic  # noqa: E402
+from symbolic import EXP3, green_mp  # noqa: E402
+from test_oracle_adjoint import gather_halo  # noqa: E402
+
+EXP6 = synthetic.moment_exponents(6)
+HALO = 24
+H3 = HALO ** 3
+SUB3 = 512
+
+
+def halo_index(x, y, z):
+    return x + HALO * y + HALO * HALO * z
+
+
+def target_index(x, y, z):
+    return (x - 8) + 8 * (y - 8) + 64 * (z - 8)
+
+
+@pytest.mark.parametrize("r", [(1.3, -2.1, 0.7), (-5.5, 0.25, 3.0), (0.0, 0.0, 4.5),
+                               (8.1, 7.9, -8.3)])
+def test_general_closed_form_matches_symbolic_derivatives_to_order_6(r):
+    ref = [float(v) for v in green_mp(r, 6)]
+    got = oracle.green_general(r, 6)
+    assert len(got) == len(EXP6) == 84
+    for n in range(7):
+        sel = [g for g, e in enumerate(EXP6) if sum(e) == n]
+        scale = max(abs(ref[g]) for g in sel)
+        for g in sel:
+            assert abs(got[g] - ref[g]) <= 2e-14 * scale, (n, EXP6[g], got[g], ref[g])
+
+
+def test_general_closed_form_equals_the_order_4_forms():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        r = rng.uniform(-9, 9, 3)
+        a = oracle.green(r, 4)
+        b = oracle.green_general(r, 4)
+        for n in range(5):
+            sel = [g for g, e in enumerate(EXP6[:35]) if sum(e) == n]
+            assert np.max(np.abs(a[sel] - b[sel])) <= 4e-15 * np.max(np.abs(a[sel]))
+
+
+def test_general_closed_form_is_harmonic_to_order_6():
+    idx = {e: g for g, e in enumerate(EXP6)}
+    rng = np.random.default_rng(4)
+    for _ in range(10):
+        G = oracle.green_general(rng.uniform(-6, 6, 3), 6)
+        # the closed form is an alternating sum: its rounding scales with the
+        # magnitude of its order, as in the comparison with sympy above
+        scale = [max(abs(G[g]) for g, f in enumerate(EXP6) if sum(f) == n) for n in range(7)]
+        for e in EXP6:
+            if sum(e) > 4:
+                continue
+            terms = [G[idx[(e[0] + 2 * (k == 0), e[1] + 2 * (k == 1), e[2] + 2 * (k == 2))]]
+                     for k in range(3)]
+            assert abs(sum(terms)) <= 1e-13 * scale[sum(e) + 2], e
+
+
+def _empty_block(nm):
+    g = synthetic._halo_coords()
+    X = (g + 0.5).T.astype(np.float64).copy()
+    return np.zeros((nm, H3)), X
+
+
+def test_mass_only_sources_give_the_total_order_result():
+    """With M_beta = 0 for |beta| > 0 both truncations keep the same terms
+    (equal up to the rounding of the two closed forms of the derivatives)."""
+    b = synthetic.monopole_block(7)
+    M = np.zeros((20, H3))
+    M[0] = b["mass"]
+    Lt, A = oracle.block_forward(M, b["com"], want_abs=True)
+    Lf = oracle.block_forward(M, b["com"], full=True)
+    assert np.all(np.abs(Lt - Lf) <= 1e-14 * A)
+
+
+def test_single_dipole_source_closed_form():
+    """One source carrying only a dipole d: L_alpha = -d . grad G_alpha(r) for
+    every output order, including order 3 (which the total-order truncation
+    drops)."""
+    M, X = _empty_block(20)
+    j = halo_index(3, 11, 14)
+    d = np.array([0.3, -0.2, 0.5])
+    M[1:4, j] = d
+    X[:, j] += [0.07, -0.03, 0.09]
+    L = oracle.block_forward(M, X, full=True)
+    t = (8, 9, 13)
+    assert oracle.in_stencil(t, (3, 11, 14))
+    i = halo_index(*t)
+    G = [float(v) for v in green_mp(X[:, i] - X[:, j], 4)]
+    idx4 = {e: g for g, e in enumerate(synthetic.moment_exponents(4))}
+    for a, e in enumerate(EXP3):
+        # s_beta = -1 for |beta| = 1: L_alpha = -sum_k d_k G_{alpha + e_k}
+        ref = -sum(d[k] * G[idx4[(e[0] + (k == 0), e[1] + (k == 1), e[2] + (k == 2))]] for k in range(3))
+        n = sum(e)
+        scale = max(abs(G[g]) for g, f in enumerate(synthetic.moment_exponents(4)) if sum(f) == n + 1)
+        assert abs(L[a, target_index(*t)] - ref) <= 1e-14 * scale * np.abs(d).sum(), e
+
+
+def test_laplace_trace_of_full_outputs():
+    b = synthetic.multipole_block(1002)
+    L, A = oracle.block_forward(b["M"], b["com"], want_abs=True, full=True)
+    comp = {e: g for g, e in enumerate(EXP3)}
+    for e in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]:
+        idx = [comp[tuple(np.add(e, 2 * np.eye(3, dtype=int)[k]))] for k in range(3)]
+        tr = L[idx[0]] + L[idx[1]] + L[idx[2]]
+        scale = A[idx[0]] + A[idx[1]] + A[idx[2]]
+        assert np.all(np.abs(tr) <= 1e-13 * scale)
+
+
+def test_full_batched_matches_block_on_gathered_halo():
+    batch, M, X = synthetic.batched_config(2, 5, missing_frac=0.5)
+    sel = np.array([0, 5], np.int32)
+    L, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True, full=True)
+    for q, t in enumerate(sel):
+        Mh, Xh = gather_halo(batch, M, X, t)
+        Lb = oracle.block_forward(Mh, Xh, full=True)
+        sl = slice(q * SUB3, (q + 1) * SUB3)
+        assert np.all(np.abs(Lb - L[:, sl]) <= 1e-13 * A[:, sl])
+
+
+def _moments_about(xc, mc, centre):
+    dd = xc - centre
+    return np.array([(mc * dd[:, 0] ** a * dd[:, 1] ** b * dd[:, 2] ** c).sum() for a, b, c in EXP3])
+
+
+def _expansion_error(scale, full, rng_seed=11):
+    rng = np.random.default_rng(rng_seed)
+    M, X = _empty_block(20)
+    j = halo_index(2, 12, 12)
+    t = (9, 12, 12)
+    assert oracle.in_stencil(t, (2, 12, 12))
+    centre = X[:, j] + np.array([0.05, -0.04, 0.03])
+    xc = centre + scale * rng.uniform(-1, 1, (8, 3))
+    mc = rng.uniform(0.5, 1.5, 8)
+    M[:, j] = _moments_about(xc, mc, centre)
+    X[:, j] = centre
+    L = oracle.block_forward(M, X, full=full)[:, target_index(*t)]
+    xt = X[:, halo_index(*t)]
+    ref = np.zeros(20)
+    for x, m in zip(xc, mc):
+        ref += m * oracle.green(xt - x, 3)
+    return L, ref
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_full_expansion_error_falls_as_a4_for_every_order(order):
+    """Every output keeps moments up to order 3: halving the source size
+    divides its error by 2^4 whatever the output order (total order: 2^(4-n))."""
+    sel = [a for a in range(20) if sum(EXP3[a]) == order]
+    errs = []
+    for s in (0.1, 0.05, 0.025):
+        L, ref = _expansion_error(s, True)
+        errs.append(np.max(np.abs(L[sel] - ref[sel])) / np.max(np.abs(ref[sel])))
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 0.75 * 16 <= e0 / e1 <= 1.3 * 16, (order, errs)
+    # and for n >= 1 it is the more accurate of the two truncations
+    if order >= 1:
+        Lt, ref = _expansion_error(0.1, False)
+        Lf, _ = _expansion_error(0.1, True)
+        assert np.max(np.abs(Lf[sel] - ref[sel])) < 0.1 * np.max(np.abs(Lt[sel] - ref[sel]))
+
+
+def test_orders_out_of_range_are_rejected():
+    with pytest.raises(ValueError):
+        oracle.green_general((1.0, 2.0, 3.0), 7)
+    assert list(itertools.islice(EXP6, 20)) == EXP3
