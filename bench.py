@@ -94,6 +94,12 @@ def main():
                     help="approximate CPU time of the oracle baseline (0: skip)")
     ap.add_argument("--tree-steps", type=int, default=10,
                     help="timed launches of each tree pass (0: skip)")
+    ap.add_argument("--full-steps", type=int, default=2,
+                    help="timed launches of the full-truncation forward (0: skip)")
+    ap.add_argument("--full-sched", type=lambda v: int(v, 0), default=None,
+                    help="schedule of the full-truncation forward (default: fastest of W8, W8+local, W8P2)")
+    ap.add_argument("--no-two-level", action="store_true",
+                    help="skip the two-level step (its parent-level forward shares the forward kernel)")
     ap.add_argument("--fwd-sched", type=lambda v: int(v, 0), default=None,
                     help="forward schedule code (skips the autotuner; e.g. 0x22 = W16 + XCD-local order)")
     ap.add_argument("--bwd-sched", type=lambda v: int(v, 0), default=None,
@@ -202,9 +208,14 @@ def main():
         tree = tree_passes(args.n, args.tree_steps, Md, Xd, L, ot, synthetic, np, torch, dev,
                            plan=plan, batch=batch)
 
+    # ------------------------------------ forward with the full truncation
+    full = None
+    if args.full_steps > 0:
+        full = full_truncation(plan, pairs, args.full_steps, Md, Xd, L, ot, torch, args.full_sched)
+
     # ------------------------------------------------- a two-level FMM step
     two_level = None
-    if args.tree_steps > 0 and args.n % 2 == 0:
+    if args.tree_steps > 0 and args.n % 2 == 0 and not args.no_two_level:
         two_level = two_level_step(args.n, args.tree_steps, plan, batch, fs, Md, Xd, L, ot, synthetic,
                                    np, torch, dev)
 
@@ -258,6 +269,7 @@ def main():
         "direct_launch_ms_per_step": round(sum_ms, 3),
         "tree_passes": tree,
         "two_level_step": two_level,
+        "full_truncation": full,
         "batched_vs_per_subgrid": per_sub,
         "cpu_baseline": cpu,
     }
@@ -360,6 +372,52 @@ def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev, plan=None, b
     log("copy 2 GiB      %.3f ms  %.0f GB/s" % (ms, out["copy_2GiB"]["gbs"]))
     del a, b
     return out
+
+
+# FP64 operations per cell pair of the full-truncation forward (every output
+# |a| <= 3 keeps every moment |b| <= 3; derivatives to order 6):
+#   as the kernel evaluates it -- r, 1/r and the radial factors D_0..D_6: 21;
+#   the derivative recursion over the 64 derivatives the trace-reduced
+#   contraction reads: 223; 16 x 16 reduced products: 512           -> 756
+#   plain formulas -- all 84 derivatives by the same recursion (443 + 21) and
+#   all 20 x 20 products (800)                                       -> 1264
+# The plain count overstates the executed work by 1.67x (its rate would pass
+# the hardware peak), so the roofline uses the reduced count.
+FULL_FLOP_REDUCED = 756
+FULL_FLOP_PLAIN = 1264
+
+
+def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None):
+    """Times the full-truncation forward on the benchmark plan: the given
+    schedule, or the fastest of three over one launch each, then `steps`
+    timed launches (HIP events on the launch stream)."""
+    stream = torch.cuda.current_stream()
+
+    def timed(sched, n):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            plan.multipole_batched_full(Md, Xd, L, sched=sched)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    cands = {ot.SCHED_W8: "W8", ot.SCHED_W8 | ot.SCHED_LOCAL: "W8+xcd-local", ot.SCHED_W8P2: "W8P2"}
+    if sched is not None:
+        cands = {sched: sched_name(sched)}
+    plan.multipole_batched_full(Md, Xd, L, sched=next(iter(cands)))  # warm-up
+    best = min(cands, key=lambda sc: timed(sc, 1)) if len(cands) > 1 else next(iter(cands))
+    ms = timed(best, steps)
+    tf = pairs * FULL_FLOP_REDUCED / (ms * 1e-3) / 1e12
+    log("full truncation %s: %.2f ms, %.3e pairs/s, %.2f TFLOP/s (reduced count)"
+        % (cands[best], ms, pairs / (ms * 1e-3), tf))
+    return {"schedule": cands[best], "mean_ms": round(ms, 3), "pairs": pairs,
+            "pairs_per_s": pairs / (ms * 1e-3),
+            "flop_per_pair": FULL_FLOP_REDUCED, "flop_per_pair_plain": FULL_FLOP_PLAIN,
+            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)}}
 
 
 def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torch, dev):

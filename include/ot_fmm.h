@@ -191,6 +191,16 @@ int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, co
 int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
                              int sched, void* stream);
 
+/* Batched forward with the full truncation: every output |a| <= 3 keeps
+ * every source moment |b| <= 3 (derivatives of G to order 6),
+ *   L_a(i) = sum_{j in S(i)} sum_{|b| <= 3} s_b M_b(j) G_{a+b}(X_i - X_j),
+ * the alternative to the total-order truncation |a| + |b| <= 3 of
+ * ot_fmm_multipole_batched (Sec. 2.1 names the FMM without its truncation;
+ * this is the other reading). Same plan, layouts, schedules (AUTO = W8) and
+ * error rules as ot_fmm_multipole_batched; L is overwritten. */
+int ot_fmm_multipole_batched_full(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                  int sched, void* stream);
+
 /* Adjoint of the batched forward for the loss l = sum gL * L:
  *   gL[20][T*512] -> gM[20][S*512] = dl/dM, gcom[3][S*512] = dl/dcom.
  * gM and gcom are OVERWRITTEN; cells of store sub-grids that no target

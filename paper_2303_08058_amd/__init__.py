@@ -67,6 +67,8 @@ _lib.ot_fmm_plan_destroy.argtypes = [_P]
 _lib.ot_fmm_plan_destroy.restype = _I
 _lib.ot_fmm_plan_pairs.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
 _lib.ot_fmm_plan_pairs.restype = _I
+_lib.ot_fmm_multipole_batched_full.argtypes = [_P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_batched_full.restype = _I
 _lib.ot_fmm_plan_set_coarse.argtypes = [_P, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64)]
 _lib.ot_fmm_plan_set_coarse.restype = _I
 _lib.ot_fmm_coarse_fine.argtypes = [_P, _P, _P, _P, _P, _P]
@@ -289,6 +291,15 @@ class Plan:
                "ot_fmm_multipole_batched")
         return L
 
+    def multipole_batched_full(self, M, com, L, sched=SCHED_AUTO, stream=None):
+        """Forward with the full truncation (every output keeps every moment
+        up to order 3); L (20, T*512) is overwritten."""
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_batched_full(self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"),
+                                                  _dptr(L, sl, "L"), int(sched), _stream(stream)),
+               "ot_fmm_multipole_batched_full")
+        return L
+
     def multipole_backward(self, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
         sm, sx, sl = self._shapes()
         _check(_lib.ot_fmm_multipole_backward(
@@ -337,6 +348,10 @@ def ot_fmm_multipole_batched(plan, M, com, L, sched=SCHED_AUTO, stream=None):
 
 def ot_fmm_multipole_backward(plan, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
     return plan.multipole_backward(M, com, gL, gM, gcom, sched, stream)
+
+
+def ot_fmm_multipole_batched_full(plan, M, com, L, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_batched_full(M, com, L, sched, stream)
 
 
 def ot_fmm_plan_set_coarse(plan, Sp, coarse, octant):

@@ -182,7 +182,7 @@ int timing_begin(ot_fmm_plan plan, int which, hipStream_t stream,
                  std::pair<hipEvent_t, hipEvent_t>* ev)
 {
     *ev = {nullptr, nullptr};
-    if (!plan->timing) return OT_FMM_OK;
+    if (!plan->timing || which < 0) return OT_FMM_OK;
     auto& pool = plan->ev_pool[which];
     size_t& used = plan->ev_used[which];
     if (used == pool.size()) {
@@ -266,6 +266,35 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
         return launch_timed<MODE_FWD_STORE, 16>(plan, 0, kp, plan->T, pers, stream);
     if (shape == OT_FMM_SCHED_W8P2)
         return launch_timed<MODE_FWD_STORE, 8, 2>(plan, 0, kp, plan->T, pers, stream);
+    return fail(OT_FMM_EINVAL, "unknown forward schedule");
+}
+
+// Forward with the full truncation: the same plan, tables and schedules as
+// the forward (not timed by the plan's events); 8 wavefronts by default.
+int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, int sched,
+                     hipStream_t stream)
+{
+    KParams kp{};
+    kp.mom = M;
+    kp.pos = com;
+    kp.mom_stride = (long)plan->S * kSub3;
+    kp.pos_stride = (long)plan->S * kSub3;
+    kp.rel = plan->d_fwd_rel;
+    kp.own_blk = plan->d_tgt;
+    kp.order = plan->d_fwd_order;
+    kp.out0 = L;
+    kp.out_stride = (long)plan->T * kSub3;
+    kp.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
+    if (sched == OT_FMM_SCHED_AUTO) sched = OT_FMM_SCHED_W8;
+    const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
+    if (sched & OT_FMM_SCHED_LOCAL) kp.order = plan->d_fwd_local;
+    const int shape = sched & kShapeMask;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FULL_STORE, 8>(plan, -1, kp, plan->T, pers, stream);
+    if (shape == OT_FMM_SCHED_W16)
+        return launch_timed<MODE_FULL_STORE, 16>(plan, -1, kp, plan->T, pers, stream);
+    if (shape == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_FULL_STORE, 8, 2>(plan, -1, kp, plan->T, pers, stream);
     return fail(OT_FMM_EINVAL, "unknown forward schedule");
 }
 
@@ -913,6 +942,21 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
         return fail(OT_FMM_EINVAL, "L overlaps an input");
     if (!valid_fwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
     return fwd_batched(plan, M, com, L, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole_batched_full(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                  int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    if (!valid_fwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
+    return fwd_full_batched(plan, M, com, L, sched, (hipStream_t)stream);
 }
 
 int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* com,

@@ -358,6 +358,74 @@ __device__ __forceinline__ void expand(const double* acc, double* full, std::int
     (expand_one<LO, LO + I>(acc, full), ...);
 }
 
+// ---------------------------------------------------------------------------
+// Full truncation: every output |a| <= 3 keeps every source moment |b| <= 3,
+// so derivatives of G are needed up to order 6. With the radial factors D_p
+// (D_0 = G = -1/r, D_{p+1} = -(2p+1) D_p / r^2, i.e. D_p = d^p G / d(r^2/2)^p)
+// and Phi^(p)_g = d^g D_p, the chain rule d_k D_p = r_k D_{p+1} gives
+//   Phi^(p)_{g+e_k} = r_k Phi^(p+1)_g + g_k Phi^(p+1)_{g-e_k},   G_g = Phi^(0)_g
+// (the same factors give the order <= 4 forms above). The recursion is
+// unrolled at compile time, reducing z first, then x, then y; the compiler
+// merges the repeated subexpressions, so each needed Phi is evaluated once.
+// The trace reduction of sources and outputs holds unchanged: every output
+// keeps complete source shells of orders 2 and 3, and the three outputs
+// L_{g+xx}, L_{g+yy}, L_{g+zz} keep the same sources.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void radial6(double x, double y, double z, double* D)
+{
+    const double r2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
+    const double ri = rsqrt_fp64(r2);
+    const double ri2 = ri * ri;
+    D[0] = -ri;
+    D[1] = ri * ri2;
+#pragma unroll
+    for (int p = 1; p < 6; ++p) D[p + 1] = (-(2.0 * p + 1.0)) * D[p] * ri2;
+}
+
+template <int P, int A, int B, int C>
+__device__ __forceinline__ double phi(const double* r, const double* D)
+{
+    if constexpr (A + B + C == 0) {
+        return D[P];
+    } else if constexpr (C > 0) {
+        const double t = r[2] * phi<P + 1, A, B, C - 1>(r, D);
+        if constexpr (C >= 2) return __builtin_fma((double)(C - 1), phi<P + 1, A, B, C - 2>(r, D), t);
+        else return t;
+    } else if constexpr (A > 0) {
+        const double t = r[0] * phi<P + 1, A - 1, B, C>(r, D);
+        if constexpr (A >= 2) return __builtin_fma((double)(A - 1), phi<P + 1, A - 2, B, C>(r, D), t);
+        else return t;
+    } else {
+        const double t = r[1] * phi<P + 1, A, B - 1, C>(r, D);
+        if constexpr (B >= 2) return __builtin_fma((double)(B - 1), phi<P + 1, A, B - 2, C>(r, D), t);
+        else return t;
+    }
+}
+
+// acc[kept slot of g] += sum_b q[b] G_{g + kRedP[b]} over all 16 reduced sources
+template <int G_, int B>
+__device__ __forceinline__ void term_full(double* acc, const double* q, const double* r, const double* D)
+{
+    if constexpr (kept(G_)) {
+        constexpr int slot = kept_slot(0, G_);
+        constexpr Exp3 e = exp_of(G_);
+        constexpr Exp3 f = exp_of(kRedP[B]);
+        acc[slot] = __builtin_fma(q[B], phi<0, e.a + f.a, e.b + f.b, e.c + f.c>(r, D), acc[slot]);
+    }
+}
+template <int G_, int... B>
+__device__ __forceinline__ void row_full(double* acc, const double* q, const double* r, const double* D,
+                                         std::integer_sequence<int, B...>)
+{
+    (term_full<G_, B>(acc, q, r, D), ...);
+}
+template <int... I>
+__device__ __forceinline__ void contract_full(double* acc, const double* q, const double* r, const double* D,
+                                              std::integer_sequence<int, I...>)
+{
+    (row_full<I>(acc, q, r, D, std::make_integer_sequence<int, kNRed>{}), ...);
+}
+
 // Adjoint epilogue: with C_g (g = 1..34, stored at C[g - 1]) the derivative
 // sums of orders 1..4 -- L'_g for the target role, F_g + E_g (E_g alone for
 // |g| = 4) for the source role -- the position gradient is
@@ -405,7 +473,8 @@ enum Mode : int {
     MODE_FWD_HALO = 1,   // single block, moments -> L
     MODE_FWD_STORE = 2,  // batched forward -> L
     MODE_B2_STORE = 3,   // adjoint, source role per store sub-grid -> gM, gX (overwrite)
-    MODE_B1_STORE = 4    // adjoint, target role per target -> gX (accumulate)
+    MODE_B1_STORE = 4,   // adjoint, target role per target -> gX (accumulate)
+    MODE_FULL_STORE = 5  // batched forward, full truncation -> L
 };
 
 struct KParams {
@@ -724,6 +793,12 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
                         green<3>(rx, ry, rz, G);
 #pragma unroll
                         for (int a = 0; a < 20; ++a) acc[a] = __builtin_fma(q[0], G[a], acc[a]);
+                    } else if constexpr (MODE == MODE_FULL_STORE) {
+                        // L_a, |a| <= 3 and |b| <= 3
+                        double D[7];
+                        radial6(rx, ry, rz, D);
+                        const double rr[3] = {rx, ry, rz};
+                        contract_full(acc, q, rr, D, std::make_integer_sequence<int, 20>{});
                     } else if constexpr (!T::adjoint) {
                         // L_a, |a| + |b| <= 3
                         double G[20];

@@ -1,0 +1,119 @@
+"""GPU parity of the batched forward with the full truncation (every output
+|alpha| <= 3 keeps every source moment |beta| <= 3; derivatives of G to
+order 6) against the CPU oracle's full truncation, through the C ABI.
+
+Criterion as for the total-order forward (tests/parity.py): per sub-grid and
+output order, max |got - ref| <= 1e-12 * max(max |ref|, 1e-2 * max A)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(__file__))
+import oracle  # noqa: E402
+import synthetic  # noqa: E402
+from parity import assert_parity  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+SUB3 = 512
+
+
+@pytest.fixture(scope="module")
+def ot():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2303_08058_amd as ot
+    return ot
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _empty(*shape):
+    import torch
+    return torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")
+
+
+# 1 W8, 2 W16, 3 W8P2; 0x10 persistent; 0x20 XCD-aware work order
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 0x11, 0x21])
+def test_full_small_periodic_with_missing(ot, sched):
+    batch, M, X = synthetic.batched_config(2, 23, missing_frac=0.5)
+    ref, A = oracle.batched_forward(batch, M, X, want_abs=True, full=True)
+    plan = ot.Plan.from_batch(batch)
+    L = _empty(20, batch["T"] * SUB3)
+    plan.multipole_batched_full(_dev(M), _dev(X), L, sched=sched)
+    got = _host(L)
+    print("full worst", assert_parity(got, ref, TOL, what="full", A=A))
+    L2 = _empty(20, batch["T"] * SUB3)
+    plan.multipole_batched_full(_dev(M), _dev(X), L2, sched=sched)
+    assert np.array_equal(_host(L2), got)
+
+
+def test_full_open_domain_differs_from_total_order_by_the_extra_terms(ot):
+    """Open 3^3 lattice: the full and total-order launches of the same plan
+    differ by the terms |alpha| + |beta| > 3 only -- on the GPU as in the
+    oracle."""
+    batch, M, X = synthetic.batched_config(3, 24, periodic=False)
+    sel = np.array([0, 13, 26], np.int32)
+    ref_f, A_f = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True, full=True)
+    ref_t, A_t = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True)
+    plan = ot.Plan.from_batch(batch)
+    dM, dX = _dev(M), _dev(X)
+    Lf, Lt = _empty(20, batch["T"] * SUB3), _empty(20, batch["T"] * SUB3)
+    plan.multipole_batched_full(dM, dX, Lf)
+    plan.multipole_batched(dM, dX, Lt)
+    cols = lambda a: a.reshape(20, -1, SUB3)[:, sel].reshape(20, -1)
+    gf, gt = cols(_host(Lf)), cols(_host(Lt))
+    assert_parity(gf, ref_f, TOL, what="full open", A=A_f)
+    # order-0 outputs keep every moment in both truncations
+    assert_parity(gf[:1], gt[:1], TOL, groups=[[0]], what="order 0 equal", A=A_f[:1])
+    # order-3 outputs: the difference is the added moment terms, as in the oracle
+    d_gpu, d_ref = gf[10:] - gt[10:], ref_f[10:] - ref_t[10:]
+    assert np.max(np.abs(d_ref)) > 1e-6 * np.max(np.abs(ref_t[10:]))
+    assert np.max(np.abs(d_gpu - d_ref)) <= 1e-12 * np.max(A_f[10:] + A_t[10:])
+
+
+def test_full_config3_sampled(ot):
+    """16^3 sub-grids, periodic, 15% of targets missing 1-9 neighbours: one
+    launch over every target, a seeded sample compared with the oracle."""
+    batch, M, X = synthetic.config3()
+    plan = ot.Plan.from_batch(batch)
+    L = _empty(20, batch["T"] * SUB3)
+    plan.multipole_batched_full(_dev(M), _dev(X), L)
+    got = _host(L)
+    assert np.all(np.isfinite(got))
+    rng = np.random.default_rng(31)
+    miss = batch["missing_targets"]
+    sel = np.sort(np.concatenate([rng.choice(miss, 6, replace=False),
+                                  rng.choice(np.setdiff1d(np.arange(batch["T"]), miss), 6,
+                                             replace=False)])).astype(np.int32)
+    ref, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True, full=True)
+    cols = got.reshape(20, -1, SUB3)[:, sel].reshape(20, -1)
+    assert_parity(cols, ref, TOL, what="full config3", A=A)
+
+
+def test_full_rejects_bad_arguments(ot):
+    batch, M, X = synthetic.batched_config(2, 25)
+    plan = ot.Plan.from_batch(batch)
+    dM, dX = _dev(M), _dev(X)
+    L = _empty(20, batch["T"] * SUB3)
+    with pytest.raises(ot.OtFmmError):
+        plan.multipole_batched_full(dM, dX, L, sched=0x07)
+    import ctypes
+    from paper_2303_08058_amd import _lib
+    # L starting inside M: rejected from the extents
+    rc = _lib.ot_fmm_multipole_batched_full(plan.handle, ctypes.c_void_p(dM.data_ptr()),
+                                            ctypes.c_void_p(dX.data_ptr()),
+                                            ctypes.c_void_p(dM.data_ptr() + 8 * 512), 0, None)
+    assert rc == ot.OT_FMM_EINVAL
