@@ -380,6 +380,31 @@ def test_config5_step_graph_sampled():
     assert bool(torch.isfinite(L).all()) and bool(torch.isfinite(gM).all()) and bool(torch.isfinite(gX).all())
 
 
+# the four (sigma1, sigma2) draws of the 32^3-sub-grid field's recipe
+# (sigma in {2, 4}, q ~ U[0.3, 1.0]), on an 8^3-sub-grid periodic store with
+# 20% of the targets missing 1-9 neighbours
+@pytest.mark.parametrize("seed,sigmas", [(2000, (2.0, 4.0)), (2001, (2.0, 2.0)),
+                                         (2002, (4.0, 4.0)), (2003, (4.0, 2.0))])
+def test_field_sweep_forward_and_adjoint_sampled(ot, seed, sigmas):
+    batch, M, X = synthetic.batched_config(8, seed, missing_frac=0.20, sigma_choices=[2.0, 4.0],
+                                           q_range=(0.3, 1.0))
+    assert (batch["field"]["sigma1"], batch["field"]["sigma2"]) == sigmas
+    w = synthetic.weights(batch["T"], seed + 1)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    NS, NT = batch["S"] * 512, batch["T"] * 512
+    L = _empty(20, NT)
+    gM, gX = _empty(20, NS), _empty(3, NS)
+    plan.multipole_batched(Md, Xd, L)
+    plan.multipole_backward(Md, Xd, wd, gM, gX)
+    sel = _sample_targets(batch, 3, 3, seed)
+    ref, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True)
+    assert_parity(_cols(_host(L), sel), ref, TOL, what="sweep L", A=A)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=sel[:3])
+    assert_parity(_cols(_host(gM), sel[:3]), gM_ref, TOL, what="sweep gM")
+    assert_parity(_cols(_host(gX), sel[:3]), gX_ref, TOL, what="sweep gX")
+
+
 def test_overlapping_outputs_rejected(ot):
     """An output whose range overlaps an input is refused with EINVAL and
     nothing is written."""
