@@ -110,17 +110,19 @@ bool pop_task(ot_fmm_executor_s* ex, Task* t)
 }
 
 // Marks the future ready and posts its continuations (called without the
-// poll lock held).
-void complete(ot_fmm_future_s* f, int status)
+// poll lock held); false if it was ready already (nothing changes then).
+bool complete(ot_fmm_future_s* f, int status)
 {
     std::vector<Task> conts;
     {
         std::lock_guard<std::mutex> lk(f->mu);
+        if (f->ready.load(std::memory_order_relaxed)) return false;
         f->status = status;
         f->ready.store(true, std::memory_order_release);
         conts.swap(f->conts);
     }
     for (const Task& t : conts) post_task(f->ex, t);
+    return true;
 }
 
 int get_event(ot_fmm_executor_s* ex, hipEvent_t* ev)
@@ -172,7 +174,7 @@ int poll_once(ot_fmm_executor_s* ex)
         ex->retry.resize(keep);
     }
     for (auto& d : done) {
-        complete(d.first, d.second);
+        (void)complete(d.first, d.second);
         future_unref(d.first);  // the registration's reference
         ex->outstanding.fetch_sub(1, std::memory_order_acq_rel);
     }
@@ -421,11 +423,7 @@ int ot_fmm_future_set_ready(ot_fmm_future f)
     g_last_error.clear();
     if (!f) return fail(OT_FMM_EINVAL, "null future");
     if (!f->host) return fail(OT_FMM_EINVAL, "future is completed by its GPU event");
-    {
-        std::lock_guard<std::mutex> lk(f->mu);
-        if (f->ready.load(std::memory_order_acquire)) return fail(OT_FMM_EINVAL, "future already ready");
-    }
-    complete(f, OT_FMM_OK);
+    if (!complete(f, OT_FMM_OK)) return fail(OT_FMM_EINVAL, "future already ready");
     return OT_FMM_OK;
 }
 

@@ -929,6 +929,25 @@ int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs)
     return OT_FMM_OK;
 }
 
+// Extents rule of the forward and adjoint entry points: outputs overlap no
+// input and no other output (the adjoint arrays only when given).
+static int check_overlaps(ot_fmm_plan plan, const double* M, const double* com, const double* L,
+                          const double* gL, const double* gM, const double* gcom)
+{
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    if (!gM) return OT_FMM_OK;
+    const double* in[4] = {M, com, gL, L};
+    const int64_t nin[4] = {20 * NS, 3 * NS, 20 * NT, 20 * NT};
+    for (int i = 0; i < 4; ++i)
+        if (overlap(gM, 20 * NS, in[i], nin[i]) || overlap(gcom, 3 * NS, in[i], nin[i]))
+            return fail(OT_FMM_EINVAL, "outputs overlap inputs");
+    if (overlap(L, 20 * NT, gL, 20 * NT)) return fail(OT_FMM_EINVAL, "L overlaps gL");
+    if (overlap(gM, 20 * NS, gcom, 3 * NS)) return fail(OT_FMM_EINVAL, "gM overlaps gcom");
+    return OT_FMM_OK;
+}
+
 int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
                              int sched, void* stream)
 {
@@ -993,10 +1012,20 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
     const bool with_bwd = gL || gM || gcom;
     if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
+    if ((rc = check_overlaps(plan, M, com, L, gL, with_bwd ? gM : nullptr, gcom))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    OT_HIP(hipEventCreate(&e0));
-    OT_HIP(hipEventCreate(&e1));
+    // the two timing events, destroyed on every return path
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    OT_HIP(hipEventCreate(&ev.a));
+    OT_HIP(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     auto time_it = [&](auto&& fn, float* ms) -> int {
         int r = fn();  // warm-up
         if (r) return r;
@@ -1047,8 +1076,6 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
         if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_PERSISTENT);
         if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_LOCAL);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc) return rc;
     plan->tuned_fwd = best_f;
     plan->tuned_bwd = best_b;
@@ -1072,6 +1099,7 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     if (!valid_fwd_sched(fwd_sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
     if (with_bwd && !valid_bwd_sched(bwd_sched))
         return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    if ((rc = check_overlaps(plan, M, com, L, gL, with_bwd ? gM : nullptr, gcom))) return rc;
     hipStream_t cs;
     OT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g = nullptr;

@@ -112,3 +112,43 @@ def test_destroy_runs_queued_tasks_and_bad_arguments():
         with pytest.raises(ot.OtFmmError) as e:
             ot.Executor(ns, nw)
         assert e.value.code == ot.OT_FMM_EINVAL
+
+
+def test_concurrent_set_ready_succeeds_exactly_once():
+    """Threads racing to make one host future ready: one succeeds, the others
+    get EINVAL, and its continuation runs once."""
+    ex = ot.Executor(nstreams=1, nworkers=2)
+    for _ in range(20):
+        f = ex.future()
+        ran = []
+        lock = threading.Lock()
+
+        def cont():
+            with lock:
+                ran.append(1)
+        f.then(cont)
+        ok, refused = [], []
+        barrier = threading.Barrier(8)
+
+        def racer():
+            barrier.wait()
+            try:
+                f.set_ready()
+                ok.append(1)
+            except ot.OtFmmError as e:
+                assert e.code == ot.OT_FMM_EINVAL
+                refused.append(1)
+        ts = [threading.Thread(target=racer) for _ in range(8)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        f.wait(5.0)
+        deadline = time.time() + 5.0
+        while not ran and time.time() < deadline:
+            time.sleep(0.001)
+        assert len(ok) == 1 and len(refused) == 7
+        time.sleep(0.01)
+        assert ran == [1]
+        f.close()
+    ex.close()

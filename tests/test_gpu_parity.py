@@ -425,6 +425,18 @@ def test_overlapping_outputs_rejected(ot):
     with pytest.raises(ot.OtFmmError) as e:
         plan.multipole_backward(Md, Xd, w, w.view(-1)[: 20 * NS].view(20, NS) if NT >= NS else w, gX)
     assert e.value.code == ot.OT_FMM_EINVAL
+    # the autotuner and the step-graph capture apply the same rule
+    L = _empty(20, NT)
+    gM = _empty(20, NS)
+    with pytest.raises(ot.OtFmmError) as e:
+        plan.autotune(Mb, Xd, L_in_M)
+    assert e.value.code == ot.OT_FMM_EINVAL
+    with pytest.raises(ot.OtFmmError) as e:
+        plan.step_graph_create(Md, Xd, L, w, gM, gM.view(-1)[: 3 * NS].view(3, NS))   # gcom inside gM
+    assert e.value.code == ot.OT_FMM_EINVAL
+    with pytest.raises(ot.OtFmmError) as e:
+        plan.step_graph_create(Md, Xd, L, L, gM, gX)   # gL aliasing L
+    assert e.value.code == ot.OT_FMM_EINVAL
     torch.cuda.synchronize()
     assert torch.equal(Mb, Md)  # untouched
 
