@@ -187,3 +187,46 @@ def test_orders_out_of_range_are_rejected():
     with pytest.raises(ValueError):
         oracle.green_general((1.0, 2.0, 3.0), 7)
     assert list(itertools.islice(EXP6, 20)) == EXP3
+
+
+def test_thirty_digit_sum_full():
+    """A target cell summed in 30-digit arithmetic over the sources of a few
+    halo planes (all other cells carry no moments), with order-6 derivatives
+    from symbolic differentiation: the full truncation's assembly and
+    rounding, independent of its closed form."""
+    import math
+
+    import mpmath
+    from symbolic import _derivative_functions
+
+    b = synthetic.multipole_block(1002)
+    M, X = b["M"].copy(), b["com"]
+    hz = np.arange(H3) // (HALO * HALO)
+    M[:, (hz < 4) | (hz > 5)] = 0.0           # sources only in halo planes z = 4, 5
+    L, A = oracle.block_forward(M, X, want_abs=True, full=True)
+    coef = []
+    for e in EXP3:
+        fac = math.factorial(e[0]) * math.factorial(e[1]) * math.factorial(e[2])
+        coef.append(mpmath.mpf((-1) ** sum(e)) / fac)
+    idx6 = {e: g for g, e in enumerate(EXP6)}
+    terms = [(a, bb, idx6[tuple(np.add(EXP3[a], EXP3[bb]))]) for a in range(20) for bb in range(20)]
+    fns = _derivative_functions(6)
+    t = (9, 12, 8)
+    i = halo_index(*t)
+    n_src = 0
+    with mpmath.workdps(30):
+        acc = [mpmath.mpf(0)] * 20
+        for hx, hy, hz_ in itertools.product(range(HALO), range(HALO), (4, 5)):
+            hj = (hx, hy, hz_)
+            if not oracle.in_stencil(t, hj):
+                continue
+            n_src += 1
+            j = halo_index(*hj)
+            r = [mpmath.mpf(float(X[k, i])) - mpmath.mpf(float(X[k, j])) for k in range(3)]
+            G = [f(*r) for f in fns]
+            for a, bb, ab in terms:
+                acc[a] += coef[bb] * mpmath.mpf(float(M[bb, j])) * G[ab]
+    assert n_src > 50
+    col = target_index(*t)
+    for a in range(20):
+        assert abs(L[a, col] - float(acc[a])) <= 2e-14 * A[a, col], (a, L[a, col], float(acc[a]))
