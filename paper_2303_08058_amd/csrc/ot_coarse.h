@@ -29,47 +29,56 @@ struct CoarseParams {
     double period[3];
 };
 
-constexpr int kCoarseBatch = 8;  // substituted slots staged together
+// One target's 512 cells, ranked by their total number of included coarse
+// cells for its pattern of substituted slots, form 8 blocks of 64 ranks. A
+// work-group of NW wavefronts takes the blocks part, part + 8/NW, ... of one
+// target (8/NW work items per target): smaller work-groups release their
+// registers and LDS as soon as their own blocks are done.
+template <int NW>
+struct CoarseShape {
+    static constexpr int parts = 8 / NW;
+    static constexpr int batch = NW;  // substituted slots staged together (LDS: NW x 9.5 KiB)
+};
 
-// One work-group (8 wavefronts) per target with substitutes. The coarse
-// cells of up to 8 substituted slots are staged in LDS at once, value-major
-// (one row of 64 coarse cells per value; measured faster than a cell-major
-// layout read with 16-byte loads, which leaves room for 6 slots only). Lane l
-// takes target cell lane_cell[order][l]: per pattern of substituted slots the
-// cells are ordered by their total number of included coarse cells, so that
-// the lanes of a wavefront run loops of similar length. A lane walks, in one
-// loop over the batch, the set bits of its cell's inclusion mask of each
-// slot (every child j = 8 s + 2 J + {0,1}^3 of coarse cell J satisfies
-// |j - i|^2 > 16, and the common parent criterion |J + 4 s - floor(i/2)|^2
-// <= 16 holds), with its accumulators in registers; the order of the sums is
-// fixed (slots, then J ascending): deterministic. The accumulators go through
-// LDS at the end so that L is read and written in cell order. (The
-// wavefronts of a work-group are unevenly loaded -- the busiest cells share
-// wavefront 0 -- and splitting cells over lanes would need a second 64 KiB
-// of LDS for the partial sums; at 0.2% of a step this was left.)
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_fine(const CoarseParams p)
+// The coarse cells of up to `batch` substituted slots are staged in LDS at
+// once, value-major (one row of 64 coarse cells per value; measured faster
+// than a cell-major layout read with 16-byte loads). Each lane takes one
+// ranked target cell, so that the lanes of a wavefront run loops of similar
+// length, and walks, in one loop over the batch, the set bits of its cell's
+// inclusion mask of each slot (every child j = 8 s + 2 J + {0,1}^3 of coarse
+// cell J satisfies |j - i|^2 > 16, and the common parent criterion
+// |J + 4 s - floor(i/2)|^2 <= 16 holds), with its accumulators in registers;
+// the order of the sums is fixed (slots, then J ascending): deterministic.
+// With 8 wavefronts (a whole target) the accumulators go through LDS at the
+// end so that L is read and written in cell order; smaller work-groups add
+// into their cells directly.
+template <int NW>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_fine(const CoarseParams p)
 {
+    using Sh = CoarseShape<NW>;
     constexpr int kNc = 3 + kNRed;                        // staged values per coarse cell
     constexpr int kNa = ModeTraits<MODE_FWD_STORE>::nacc;  // kept L_a of the reduced form
     constexpr int kSlotVals = kNc * 64;
-    __shared__ double s_src[kCoarseBatch * kSlotVals];
-    __shared__ int s_slot[kCoarseBatch];
-    static_assert(kNa * kSub3 <= kCoarseBatch * kSlotVals, "epilogue reuses the staging buffer");
+    __shared__ double s_src[Sh::batch * kSlotVals];
+    __shared__ int s_slot[Sh::batch];
+    static_assert(NW != 8 || kNa * kSub3 <= Sh::batch * kSlotVals, "epilogue reuses the staging buffer");
     const int tid = threadIdx.x;
     const int4 it = p.items[blockIdx.x];  // uniform
     const int t = it.x;
-    const int cell = p.lane_cell[(long)it.y * kSub3 + tid];
+    const int order = it.y >> 3, part = it.y & 7;
+    const int rank = 64 * (part + Sh::parts * (tid >> 6)) + (tid & 63);
+    const int cell = p.lane_cell[(long)order * kSub3 + rank];
     const long own = (long)p.own_blk[t] * kSub3 + cell;
     const double xi = p.pos[own], yi = p.pos[p.pos_stride + own], zi = p.pos[2 * p.pos_stride + own];
     double acc[kNa];
 #pragma unroll
     for (int a = 0; a < kNa; ++a) acc[a] = 0.0;
 
-    for (int b0 = 0; b0 < it.w; b0 += kCoarseBatch) {
-        const int nb = (it.w - b0 < kCoarseBatch) ? it.w - b0 : kCoarseBatch;
+    for (int b0 = 0; b0 < it.w; b0 += Sh::batch) {
+        const int nb = (it.w - b0 < Sh::batch) ? it.w - b0 : Sh::batch;
         const int4* ent = p.entries + it.z + b0;
         __syncthreads();  // the previous batch is no longer read
-        for (int v = tid; v < nb * kSlotVals; v += 512) {
+        for (int v = tid; v < nb * kSlotVals; v += NW * 64) {
             const int b = v / kSlotVals, r = v - b * kSlotVals;
             const int k = r >> 6, J = r & 63;
             const int4 e = ent[b];
@@ -115,16 +124,20 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k
             contract_red<0, TRUNC3>(acc, f + 3, G, std::make_integer_sequence<int, 20>{});
         }
     }
-    // back to cell order through LDS
-    __syncthreads();
+    int oc = cell;
+    if constexpr (NW == 8) {
+        // back to cell order through LDS
+        __syncthreads();
 #pragma unroll
-    for (int a = 0; a < kNa; ++a) s_src[a * kSub3 + cell] = acc[a];
-    __syncthreads();
+        for (int a = 0; a < kNa; ++a) s_src[a * kSub3 + cell] = acc[a];
+        __syncthreads();
 #pragma unroll
-    for (int a = 0; a < kNa; ++a) acc[a] = s_src[a * kSub3 + tid];
+        for (int a = 0; a < kNa; ++a) acc[a] = s_src[a * kSub3 + tid];
+        oc = tid;
+    }
     double L[20];
     expand<0>(acc, L, std::make_integer_sequence<int, 20>{});
-    const long ob = (long)t * kSub3 + tid;
+    const long ob = (long)t * kSub3 + oc;
 #pragma unroll
     for (int a = 0; a < 20; ++a) p.out[a * p.out_stride + ob] += L[a];
 }

@@ -55,6 +55,13 @@
 #include "ot_interact.h"
 #include "ot_coarse.h"
 
+namespace {
+// wavefronts per work-group of the coarse substitutes: 8, one target per
+// work-group (4 and 2, a part of a target each, measured 1.35x and 1.85x
+// slower on the 32768-sub-grid workload: their staging is repeated per part)
+constexpr int kCoarseWaves = 8;
+}  // namespace
+
 
 // ===========================================================================
 // Host side
@@ -167,7 +174,7 @@ struct ot_fmm_plan_s {
     // coarse substitutes for missing neighbours (ot_fmm_plan_set_coarse)
     std::vector<uint32_t> missing;  // [T] bit s: slot s has no fine neighbour
     int32_t Sp_coarse = 0;
-    int n_coarse_targets = 0;
+    int n_coarse_items = 0;  // work items: targets with substitutes x parts
     int4* d_cf_items = nullptr;     // {target, lane order, first entry, entries}, most work first
     int4* d_cf_entries = nullptr;   // {slot, coarse node, octant, 0}
     int* d_cf_cells = nullptr;      // [orders][512] target cell of each lane
@@ -802,10 +809,12 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
         }
     }
     // per pattern of substituted slots: the target cells in lane order, by
-    // decreasing total count, and the summed loop trips of the 8 wavefronts
+    // decreasing total count, and the loop trips of each block of 64 ranks
+    // (its first cell's count); work items are the parts of a target
+    constexpr int kParts = CoarseShape<kCoarseWaves>::parts;
     std::unordered_map<uint32_t, int> pattern_id;
     std::vector<int> cells;
-    std::vector<int64_t> pattern_cost;
+    std::vector<std::array<int64_t, 8>> pattern_blocks;
     std::vector<int4> items, entries;
     std::vector<int64_t> item_cost;
     int64_t total = 0;
@@ -823,7 +832,7 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
         auto f = pattern_id.find(pat);
         int id;
         if (f == pattern_id.end()) {
-            id = (int)pattern_cost.size();
+            id = (int)pattern_blocks.size();
             pattern_id.emplace(pat, id);
             std::vector<int> tot(kSub3, 0), order(kSub3);
             for (int q = 0; q < 27; ++q)
@@ -832,15 +841,19 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
             for (int c = 0; c < kSub3; ++c) order[c] = c;
             std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return tot[x] > tot[y]; });
             cells.insert(cells.end(), order.begin(), order.end());
-            int64_t cost = 0;
-            for (int w = 0; w < kSub3 / 64; ++w) cost += tot[order[64 * w]];
-            pattern_cost.push_back(cost);
+            std::array<int64_t, 8> blk{};
+            for (int w = 0; w < 8; ++w) blk[w] = tot[order[64 * w]];
+            pattern_blocks.push_back(blk);
         } else {
             id = f->second;
         }
         const int n = (int)entries.size() - first;
-        items.push_back(make_int4(t, id, first, n));
-        item_cost.push_back(pattern_cost[id] + 8 * n);  // + staging
+        for (int part = 0; part < kParts; ++part) {
+            int64_t cost = 8 * n;  // staging
+            for (int w = part; w < 8; w += kParts) cost += pattern_blocks[id][w];
+            items.push_back(make_int4(t, id * 8 + part, first, n));
+            item_cost.push_back(cost);
+        }
     }
     std::vector<int> idx(items.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
@@ -882,7 +895,7 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
     plan->d_cf_cells = d_cells;
     plan->d_cf_mask = d_mask;
     plan->Sp_coarse = Sp;
-    plan->n_coarse_targets = (int)items.size();
+    plan->n_coarse_items = (int)items.size();
     if (pairs) *pairs = total;
     return OT_FMM_OK;
 }
@@ -900,7 +913,7 @@ int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, co
                   NP = (int64_t)plan->Sp_coarse * kSub3;
     if (overlap(L, 20 * NT, com, 3 * NS) || overlap(L, 20 * NT, Mp, 20 * NP) || overlap(L, 20 * NT, comp, 3 * NP))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
-    if (plan->n_coarse_targets == 0) return OT_FMM_OK;
+    if (plan->n_coarse_items == 0) return OT_FMM_OK;
     CoarseParams cp{};
     cp.pos = com;
     cp.pos_stride = NS;
@@ -916,7 +929,8 @@ int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, co
     cp.out = L;
     cp.out_stride = NT;
     for (int k = 0; k < 3; ++k) cp.period[k] = plan->period[k];
-    hipLaunchKernelGGL(k_coarse_fine, dim3((unsigned)plan->n_coarse_targets), dim3(512), 0, (hipStream_t)stream, cp);
+    hipLaunchKernelGGL(k_coarse_fine<kCoarseWaves>, dim3((unsigned)plan->n_coarse_items), dim3(kCoarseWaves * 64), 0,
+                       (hipStream_t)stream, cp);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
 }
