@@ -63,10 +63,10 @@ def _load():
     for f in (lib.orc_batched_forward, lib.orc_batched_forward_full):
         f.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
         f.restype = i
-    lib.orc_batched_forward_cs.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
-    lib.orc_batched_forward_cs.restype = i
-    lib.orc_batched_backward.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
-    lib.orc_batched_backward.restype = i
+    for f in (lib.orc_batched_forward_cs, lib.orc_batched_forward_cs_full,
+              lib.orc_batched_backward, lib.orc_batched_backward_full):
+        f.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
+        f.restype = i
     lib.orc_coarse_fine.argtypes = [i, i, P, P, P, P, P, i, P, P, P, P, P, i, P, P, i]
     lib.orc_coarse_fine.restype = i
     lib.orc_m2m.argtypes = [i, i, P, P, P, P, i, P, P, i]
@@ -111,13 +111,13 @@ def green(r, order: int = 4) -> np.ndarray:
 
 
 def green_general(r, order: int = 6) -> np.ndarray:
-    """d^gamma(-1/|r|) for |gamma| <= order (<= 6) from the general closed form
+    """d^gamma(-1/|r|) for |gamma| <= order (<= 7) from the general closed form
     (Hobson's formula), graded-lex order."""
     n = (order + 1) * (order + 2) * (order + 3) // 6
     r = _f64(r)
     out = np.zeros(n, np.float64)
     if _load().orc_green_general(_ptr(r), order, _ptr(out)):
-        raise ValueError("order must be in 0..6")
+        raise ValueError("order must be in 0..7")
     return out
 
 
@@ -172,8 +172,9 @@ def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: in
     return (L, A) if want_abs else L
 
 
-def batched_forward_cs(batch, M, Xre, Xim, tsel=None, nthreads: int = 0):
-    """Complex-position forward (for complex-step derivatives). Returns (Lre, Lim)."""
+def batched_forward_cs(batch, M, Xre, Xim, tsel=None, nthreads: int = 0, full: bool = False):
+    """Complex-position forward (for complex-step derivatives). Returns (Lre, Lim).
+    full=True: the full truncation."""
     S, T, tgt, nbr, shift, period = _batch_args(batch)
     tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
     M = _f64(M)
@@ -181,18 +182,18 @@ def batched_forward_cs(batch, M, Xre, Xim, tsel=None, nthreads: int = 0):
     Xim = _f64(Xim)
     Lre = np.zeros((NM, len(tsel) * SUB3), np.float64)
     Lim = np.zeros_like(Lre)
-    rc = _load().orc_batched_forward_cs(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift),
-                                        _ptr(period), _ptr(M), _ptr(Xre), _ptr(Xim),
-                                        _ptr(tsel), len(tsel), _ptr(Lre), _ptr(Lim),
-                                        nthreads)
+    fn = _load().orc_batched_forward_cs_full if full else _load().orc_batched_forward_cs
+    rc = fn(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M), _ptr(Xre), _ptr(Xim),
+            _ptr(tsel), len(tsel), _ptr(Lre), _ptr(Lim), nthreads)
     if rc:
         raise ValueError("orc_batched_forward_cs rejected its arguments")
     return Lre, Lim
 
 
-def batched_backward(batch, M, X, gL, ssel=None, nthreads: int = 0):
+def batched_backward(batch, M, X, gL, ssel=None, nthreads: int = 0, full: bool = False):
     """Gradients of sum(gL * L) w.r.t. moments and centres of mass of the
-    selected store sub-grids. Returns gM (20, nsel*512), gX (3, nsel*512)."""
+    selected store sub-grids. Returns gM (20, nsel*512), gX (3, nsel*512).
+    full=True: of the full-truncation forward."""
     S, T, tgt, nbr, shift, period = _batch_args(batch)
     ssel = np.arange(S, dtype=np.int32) if ssel is None else _i32(ssel)
     M = _f64(M)
@@ -201,9 +202,9 @@ def batched_backward(batch, M, X, gL, ssel=None, nthreads: int = 0):
     assert gL.shape == (NM, T * SUB3)
     gM = np.zeros((NM, len(ssel) * SUB3), np.float64)
     gX = np.zeros((3, len(ssel) * SUB3), np.float64)
-    rc = _load().orc_batched_backward(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period),
-                                      _ptr(M), _ptr(X), _ptr(gL), _ptr(ssel), len(ssel),
-                                      _ptr(gM), _ptr(gX), nthreads)
+    fn = _load().orc_batched_backward_full if full else _load().orc_batched_backward
+    rc = fn(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M), _ptr(X), _ptr(gL),
+            _ptr(ssel), len(ssel), _ptr(gM), _ptr(gX), nthreads)
     if rc:
         raise ValueError("orc_batched_backward rejected its arguments")
     return gM, gX

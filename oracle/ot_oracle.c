@@ -156,6 +156,88 @@ static void local_coords(int c, int l[3])
 }
 
 /* ---------------------------------------------------------------------------
+ * "Full" truncation, the variant beside the total-order one: every output
+ * order |alpha| <= 3 keeps every source moment |beta| <= 3, so derivatives of
+ * G are needed to order 6:
+ *   L_alpha(i) = sum_{j in S(i)} sum_{|beta| <= 3} s_beta M_beta(j) G_{alpha+beta}(X_i - X_j)
+ * Derivatives of any order come from the general closed form of d^gamma (1/r)
+ * (Hobson's formula), independent of the Kronecker-delta forms above: for
+ * gamma = (a, b, c), n = a + b + c,
+ *   d^gamma (1/r) = sum_{i <= a/2, j <= b/2, k <= c/2}
+ *       (-1)^(n-m) (2n-2m-1)!! r^-(2n-2m+1) h(a,i) h(b,j) h(c,k) x^(a-2i) y^(b-2j) z^(c-2k),
+ *   m = i + j + k,  h(a,i) = a! / (2^i i! (a-2i)!),  (-1)!! = 1,
+ * and G_gamma = -d^gamma (1/r).
+ * ------------------------------------------------------------------------- */
+#define NGA 120 /* derivatives up to order 7 (the full truncation and its adjoint) */
+static int g6_exp[NGA][3];
+static int g6_sum[NM][NM]; /* index of alpha + beta among the NGA */
+/* the terms of the closed form of each derivative, tabulated once:
+ * coefficient, power of 1/r, powers of x, y, z (in the order i, j, k) */
+#define MAXTERMS 16
+static int g6_nterm[NGA];
+static double g6_coef[NGA][MAXTERMS];
+static int g6_pow[NGA][MAXTERMS][4];
+static int g6_ready = 0;
+static double double_factorial(int n);
+static double hobson_h(int a, int i);
+
+static void init_tables6(void)
+{
+    if (g6_ready) return;
+    init_tables();
+    int k = 0;
+    for (int n = 0; n <= 7; ++n)
+        for (int a = n; a >= 0; --a)
+            for (int b = n - a; b >= 0; --b) {
+                g6_exp[k][0] = a;
+                g6_exp[k][1] = b;
+                g6_exp[k][2] = n - a - b;
+                ++k;
+            }
+    for (int g = 0; g < NM; ++g)
+        for (int h = 0; h < NM; ++h) {
+            int e[3] = {g_exp[g][0] + g_exp[h][0], g_exp[g][1] + g_exp[h][1], g_exp[g][2] + g_exp[h][2]};
+            g6_sum[g][h] = -1;
+            for (int q = 0; q < NGA; ++q)
+                if (g6_exp[q][0] == e[0] && g6_exp[q][1] == e[1] && g6_exp[q][2] == e[2]) g6_sum[g][h] = q;
+        }
+    for (int g = 0; g < NGA; ++g) {
+        int a = g6_exp[g][0], b = g6_exp[g][1], c = g6_exp[g][2], n = a + b + c, t = 0;
+        for (int i = 0; 2 * i <= a; ++i)
+            for (int j = 0; 2 * j <= b; ++j)
+                for (int k = 0; 2 * k <= c; ++k) {
+                    int m = i + j + k;
+                    g6_coef[g][t] = (((n - m) & 1) ? -1.0 : 1.0) * double_factorial(2 * n - 2 * m - 1) *
+                                    hobson_h(a, i) * hobson_h(b, j) * hobson_h(c, k);
+                    g6_pow[g][t][0] = 2 * n - 2 * m + 1;
+                    g6_pow[g][t][1] = a - 2 * i;
+                    g6_pow[g][t][2] = b - 2 * j;
+                    g6_pow[g][t][3] = c - 2 * k;
+                    ++t;
+                }
+        g6_nterm[g] = t;
+    }
+    g6_ready = 1;
+}
+
+static double double_factorial(int n)
+{
+    double f = 1.0;
+    for (int k = n; k > 1; k -= 2) f *= k;
+    return f;
+}
+
+static double hobson_h(int a, int i) { return factorial(a) / (ldexp(1.0, i) * factorial(i) * factorial(a - 2 * i)); }
+
+/* index of the exponent (a, b, c) in the graded-lex enumeration */
+static int gidx(int a, int b, int c)
+{
+    int n = a + b + c, k = n > 0 ? ncomp(n - 1) : 0;
+    for (int ap = n; ap > a; --ap) k += n - ap + 1;
+    return k + (n - a) - b;
+}
+
+/* ---------------------------------------------------------------------------
  * Scalar-generic core: real and complex instantiations
  * ------------------------------------------------------------------------- */
 #define SC double
@@ -178,106 +260,11 @@ static void local_coords(int c, int l[3])
 #undef FN
 #undef cabs_generic
 
-/* ---------------------------------------------------------------------------
- * "Full" truncation, the variant beside the total-order one: every output
- * order |alpha| <= 3 keeps every source moment |beta| <= 3, so derivatives of
- * G are needed to order 6:
- *   L_alpha(i) = sum_{j in S(i)} sum_{|beta| <= 3} s_beta M_beta(j) G_{alpha+beta}(X_i - X_j)
- * Derivatives of any order come from the general closed form of d^gamma (1/r)
- * (Hobson's formula), independent of the Kronecker-delta forms above: for
- * gamma = (a, b, c), n = a + b + c,
- *   d^gamma (1/r) = sum_{i <= a/2, j <= b/2, k <= c/2}
- *       (-1)^(n-m) (2n-2m-1)!! r^-(2n-2m+1) h(a,i) h(b,j) h(c,k) x^(a-2i) y^(b-2j) z^(c-2k),
- *   m = i + j + k,  h(a,i) = a! / (2^i i! (a-2i)!),  (-1)!! = 1,
- * and G_gamma = -d^gamma (1/r).
- * ------------------------------------------------------------------------- */
-#define NG6 84 /* derivatives up to order 6 */
-static int g6_exp[NG6][3];
-static int g6_sum[NM][NM]; /* index of alpha + beta among the NG6 */
-static int g6_ready = 0;
-
-static void init_tables6(void)
-{
-    if (g6_ready) return;
-    init_tables();
-    int k = 0;
-    for (int n = 0; n <= 6; ++n)
-        for (int a = n; a >= 0; --a)
-            for (int b = n - a; b >= 0; --b) {
-                g6_exp[k][0] = a;
-                g6_exp[k][1] = b;
-                g6_exp[k][2] = n - a - b;
-                ++k;
-            }
-    for (int g = 0; g < NM; ++g)
-        for (int h = 0; h < NM; ++h) {
-            int e[3] = {g_exp[g][0] + g_exp[h][0], g_exp[g][1] + g_exp[h][1], g_exp[g][2] + g_exp[h][2]};
-            g6_sum[g][h] = -1;
-            for (int q = 0; q < NG6; ++q)
-                if (g6_exp[q][0] == e[0] && g6_exp[q][1] == e[1] && g6_exp[q][2] == e[2]) g6_sum[g][h] = q;
-        }
-    g6_ready = 1;
-}
-
-static double double_factorial(int n)
-{
-    double f = 1.0;
-    for (int k = n; k > 1; k -= 2) f *= k;
-    return f;
-}
-
-static double hobson_h(int a, int i) { return factorial(a) / (ldexp(1.0, i) * factorial(i) * factorial(a - 2 * i)); }
-
-static void green_general(const double r[3], int order, double *G)
-{
-    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    double rinv = 1.0 / sqrt(r2);
-    double pw[3][7];
-    for (int d = 0; d < 3; ++d) {
-        pw[d][0] = 1.0;
-        for (int p = 1; p <= 6; ++p) pw[d][p] = pw[d][p - 1] * r[d];
-    }
-    double rp[14]; /* rinv^q */
-    rp[0] = 1.0;
-    for (int q = 1; q < 14; ++q) rp[q] = rp[q - 1] * rinv;
-    int n_out = ncomp(order);
-    for (int g = 0; g < n_out; ++g) {
-        int a = g6_exp[g][0], b = g6_exp[g][1], c = g6_exp[g][2];
-        int n = a + b + c;
-        double v = 0.0;
-        for (int i = 0; 2 * i <= a; ++i)
-            for (int j = 0; 2 * j <= b; ++j)
-                for (int k = 0; 2 * k <= c; ++k) {
-                    int m = i + j + k;
-                    double coef = (((n - m) & 1) ? -1.0 : 1.0) * double_factorial(2 * n - 2 * m - 1) *
-                                  hobson_h(a, i) * hobson_h(b, j) * hobson_h(c, k);
-                    v += coef * rp[2 * n - 2 * m + 1] * pw[0][a - 2 * i] * pw[1][b - 2 * j] * pw[2][c - 2 * k];
-                }
-        G[g] = -v;
-    }
-}
-
-/* One pair, full truncation (moments up to order mmax for every output). */
-static void pair_forward_full(const double Xi[3], const double Xj[3], const double *Mj, int nm, int mmax,
-                              double *L, double *Aabs)
-{
-    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
-    double G[NG6];
-    green_general(r, 6, G);
-    for (int a = 0; a < NM; ++a)
-        for (int b = 0; b < nm; ++b) {
-            if (order_of(b) > mmax) continue;
-            double term = taylor_sign(b) * Mj[b] * G[g6_sum[a][b]];
-            L[a] += term;
-            if (Aabs) Aabs[a] += fabs(term);
-        }
-}
-
 static void pair_forward_any(int full, const double Xi[3], const double Xj[3], const double *Mj, int nm,
                              int mmax, double *L, double *Aabs)
 {
     if (full)
-        pair_forward_full(Xi, Xj, Mj, nm, mmax, L, Aabs);
+        pair_forward_full_re(Xi, Xj, Mj, nm, mmax, L, Aabs);
     else
         pair_forward_re(Xi, Xj, Mj, nm, mmax, L, Aabs);
 }
@@ -315,12 +302,12 @@ void orc_green(const double r[3], int order, double *G)
 
 int orc_in_stencil(const int hi[3], const int hj[3]) { return in_stencil(hi, hj); }
 
-/* G_gamma for |gamma| <= order (order <= 6) from the general closed form. */
+/* G_gamma for |gamma| <= order (order <= 7) from the general closed form. */
 int orc_green_general(const double r[3], int order, double *G)
 {
-    if (order < 0 || order > 6) return -1;
+    if (order < 0 || order > 7) return -1;
     init_tables6();
-    green_general(r, order, G);
+    green_general_re(r, order, G);
     return 0;
 }
 
@@ -561,12 +548,13 @@ int orc_coarse_fine(int S, int T, const int32_t *tgt, const int32_t *nbr, const 
 
 /* Same sum with complex centres of mass X = Xre + i Xim (moments real), for
  * complex-step differentiation: d(sum w L)/dX_c,k = Im(sum w L(X + i h e_ck))/h. */
-int orc_batched_forward_cs(int S, int T, const int32_t *tgt, const int32_t *nbr,
-                           const int8_t *shift, const double *period, const double *M,
-                           const double *Xre, const double *Xim, const int32_t *tsel,
-                           int nsel, double *Lre, double *Lim, int nthreads)
+static int batched_forward_cs(int full, int S, int T, const int32_t *tgt, const int32_t *nbr,
+                              const int8_t *shift, const double *period, const double *M,
+                              const double *Xre, const double *Xim, const int32_t *tsel,
+                              int nsel, double *Lre, double *Lim, int nthreads)
 {
     init_tables();
+    init_tables6();
     if (check_batch(S, T, tgt, nbr)) return -1;
     for (int q = 0; q < nsel; ++q)
         if (tsel[q] < 0 || tsel[q] >= T) return -1;
@@ -603,7 +591,10 @@ int orc_batched_forward_cs(int S, int T, const int32_t *tgt, const int32_t *nbr,
                         Xj[k] = (Xre[k * NS + jidx] + sh[k]) + I * Xim[k * NS + jidx];
                     double Mj[NM];
                     for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
-                    pair_forward_cx(Xi, Xj, Mj, NM, 3, acc, NULL);
+                    if (full)
+                        pair_forward_full_cx(Xi, Xj, Mj, NM, 3, acc, NULL);
+                    else
+                        pair_forward_cx(Xi, Xj, Mj, NM, 3, acc, NULL);
                 }
             }
             for (int a = 0; a < NM; ++a) {
@@ -612,6 +603,22 @@ int orc_batched_forward_cs(int S, int T, const int32_t *tgt, const int32_t *nbr,
             }
         }
     return 0;
+}
+
+int orc_batched_forward_cs(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                           const int8_t *shift, const double *period, const double *M,
+                           const double *Xre, const double *Xim, const int32_t *tsel,
+                           int nsel, double *Lre, double *Lim, int nthreads)
+{
+    return batched_forward_cs(0, S, T, tgt, nbr, shift, period, M, Xre, Xim, tsel, nsel, Lre, Lim, nthreads);
+}
+
+int orc_batched_forward_cs_full(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                                const int8_t *shift, const double *period, const double *M,
+                                const double *Xre, const double *Xim, const int32_t *tsel,
+                                int nsel, double *Lre, double *Lim, int nthreads)
+{
+    return batched_forward_cs(1, S, T, tgt, nbr, shift, period, M, Xre, Xim, tsel, nsel, Lre, Lim, nthreads);
 }
 
 /* ---------------------------------------------------------------------------
@@ -649,12 +656,32 @@ static void pair_gradients(const double Xi[3], const double Xj[3], const double 
         }
 }
 
-int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
-                         const int8_t *shift, const double *period, const double *M,
-                         const double *X, const double *gL, const int32_t *ssel, int nsel,
-                         double *gM, double *gX, int nthreads)
+/* The same with the full truncation (all |a|, |b| <= 3; G to order 7). */
+static void pair_gradients_full(const double Xi[3], const double Xj[3], const double *w,
+                                const double *Mj, double dM[NM], double dX[3])
+{
+    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
+    double G[NGA];
+    green_general_re(r, 7, G);
+    for (int b = 0; b < NM; ++b) dM[b] = 0.0;
+    dX[0] = dX[1] = dX[2] = 0.0;
+    for (int a = 0; a < NM; ++a)
+        for (int b = 0; b < NM; ++b) {
+            int e[3] = {g_exp[a][0] + g_exp[b][0], g_exp[a][1] + g_exp[b][1], g_exp[a][2] + g_exp[b][2]};
+            dM[b] += taylor_sign(b) * w[a] * G[gidx(e[0], e[1], e[2])];
+            for (int k = 0; k < 3; ++k)
+                dX[k] += w[a] * taylor_sign(b) * Mj[b] *
+                         G[gidx(e[0] + (k == 0), e[1] + (k == 1), e[2] + (k == 2))];
+        }
+}
+
+static int batched_backward(int full, int S, int T, const int32_t *tgt, const int32_t *nbr,
+                            const int8_t *shift, const double *period, const double *M,
+                            const double *X, const double *gL, const int32_t *ssel, int nsel,
+                            double *gM, double *gX, int nthreads)
 {
     init_tables();
+    init_tables6();
     if (check_batch(S, T, tgt, nbr)) return -1;
     for (int q = 0; q < nsel; ++q)
         if (ssel[q] < 0 || ssel[q] >= S) return -1;
@@ -707,7 +734,10 @@ int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
                     size_t iidx = (size_t)tgt[t] * SUB3 + ci;
                     double Xi[3] = {X[iidx], X[NS + iidx], X[2 * NS + iidx]};
                     for (int a = 0; a < NM; ++a) w[a] = gL[a * NT + (size_t)t * SUB3 + ci];
-                    pair_gradients(Xi, Xj, w, Mc, dM, dX);
+                    if (full)
+                        pair_gradients_full(Xi, Xj, w, Mc, dM, dX);
+                    else
+                        pair_gradients(Xi, Xj, w, Mc, dM, dX);
                     for (int b = 0; b < NM; ++b) accM[b] += dM[b];
                     for (int k = 0; k < 3; ++k) accX[k] -= dX[k];
                 }
@@ -734,7 +764,10 @@ int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
                                         X[2 * NS + jidx] + sh[2]};
                         double Mj[NM];
                         for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
-                        pair_gradients(Xc, Xj, w, Mj, dM, dX);
+                        if (full)
+                            pair_gradients_full(Xc, Xj, w, Mj, dM, dX);
+                        else
+                            pair_gradients(Xc, Xj, w, Mj, dM, dX);
                         for (int k = 0; k < 3; ++k) accX[k] += dX[k];
                     }
                 }
@@ -746,6 +779,22 @@ int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
         free(rel_slot);
     }
     return 0;
+}
+
+int orc_batched_backward(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                         const int8_t *shift, const double *period, const double *M,
+                         const double *X, const double *gL, const int32_t *ssel, int nsel,
+                         double *gM, double *gX, int nthreads)
+{
+    return batched_backward(0, S, T, tgt, nbr, shift, period, M, X, gL, ssel, nsel, gM, gX, nthreads);
+}
+
+int orc_batched_backward_full(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                              const int8_t *shift, const double *period, const double *M,
+                              const double *X, const double *gL, const int32_t *ssel, int nsel,
+                              double *gM, double *gX, int nthreads)
+{
+    return batched_backward(1, S, T, tgt, nbr, shift, period, M, X, gL, ssel, nsel, gM, gX, nthreads);
 }
 
 /* ---------------------------------------------------------------------------

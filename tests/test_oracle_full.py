@@ -11,7 +11,14 @@ output order (the total-order truncation: like a^(4-n)). CPU only.
 Planted mistakes each fail one of these: a wrong sign or double factorial
 in the general closed form (symbolic), a dropped Hobson term (symbolic,
 harmonic), a truncation still at |alpha| + |beta| <= 3 (direct summation),
-a wrong multi-index sum table (symbolic via the single-source closed form)."""
+a wrong multi-index sum table (symbolic via the single-source closed form);
+in the adjoint, a transposed gradient component (complex step, central
+differences) and a dropped s_beta in the moment gradient (dot product).
+
+The adjoint (derivatives to order 7) is pinned by the dot-product test (the
+loss is linear in the moments), complex-step derivatives of the full forward
+(step 1e-30, no cancellation), central differences and translation
+invariance (the position gradients sum to zero)."""
 import itertools
 import os
 import sys
@@ -50,6 +57,18 @@ def test_general_closed_form_matches_symbolic_derivatives_to_order_6(r):
         scale = max(abs(ref[g]) for g in sel)
         for g in sel:
             assert abs(got[g] - ref[g]) <= 2e-14 * scale, (n, EXP6[g], got[g], ref[g])
+
+
+@pytest.mark.parametrize("r", [(1.3, -2.1, 0.7), (-6.5, 3.25, 4.0)])
+def test_general_closed_form_matches_symbolic_derivatives_at_order_7(r):
+    """Order 7 enters the position gradient of the full truncation."""
+    exp7 = synthetic.moment_exponents(7)
+    ref = [float(v) for v in green_mp(r, 7)]
+    got = oracle.green_general(r, 7)
+    sel = [g for g, e in enumerate(exp7) if sum(e) == 7]
+    scale = max(abs(ref[g]) for g in sel)
+    for g in sel:
+        assert abs(got[g] - ref[g]) <= 2e-14 * scale, (exp7[g], got[g], ref[g])
 
 
 def test_general_closed_form_equals_the_order_4_forms():
@@ -185,7 +204,7 @@ def test_full_expansion_error_falls_as_a4_for_every_order(order):
 
 def test_orders_out_of_range_are_rejected():
     with pytest.raises(ValueError):
-        oracle.green_general((1.0, 2.0, 3.0), 7)
+        oracle.green_general((1.0, 2.0, 3.0), 8)
     assert list(itertools.islice(EXP6, 20)) == EXP3
 
 
@@ -230,3 +249,82 @@ def test_thirty_digit_sum_full():
     col = target_index(*t)
     for a in range(20):
         assert abs(L[a, col] - float(acc[a])) <= 2e-14 * A[a, col], (a, L[a, col], float(acc[a]))
+
+
+# ---------------------------------------------------------------------------
+# adjoint of the full truncation (derivatives to order 7)
+# ---------------------------------------------------------------------------
+from test_oracle_adjoint import small_open_case  # noqa: E402
+
+
+def _loss_full(batch, M, X, w):
+    return float(np.sum(w * oracle.batched_forward(batch, M, X, full=True)))
+
+
+def _cols(a, sel):
+    return a.reshape(a.shape[0], -1, SUB3)[:, sel].reshape(a.shape[0], -1)
+
+
+def test_full_moment_gradient_dot_product():
+    """V nonzero on two store sub-grids only (one a target, one not)."""
+    batch, M, X = small_open_case(targets=(13, 4), missing=((13, 5),))
+    w = synthetic.weights(batch["T"], 15)
+    ssel = np.array([13, 12], np.int32)
+    gM, gX = oracle.batched_backward(batch, M, X, w, ssel=ssel, full=True)
+    rng = np.random.default_rng(18)
+    V = np.zeros_like(M)
+    for s_ in ssel:
+        V[:, s_ * SUB3:(s_ + 1) * SUB3] = rng.standard_normal((20, SUB3)) * np.abs(M).max(axis=1, keepdims=True)
+    l0 = _loss_full(batch, M, X, w)
+    l1 = _loss_full(batch, M + V, X, w)
+    lv = _loss_full(batch, V, X, w)          # the loss is linear in M
+    dot = float(np.sum(gM * _cols(V, ssel)))
+    assert abs((l1 - l0) - dot) <= 1e-10 * abs(dot)
+    assert abs(lv - dot) <= 1e-12 * abs(dot)
+    # and it is not the total-order gradient
+    gM_t, _ = oracle.batched_backward(batch, M, X, w, ssel=ssel)
+    assert np.max(np.abs(gM - gM_t)) > 1e-6 * np.max(np.abs(gM))
+
+
+def test_full_position_gradient_complex_step():
+    batch, M, X = small_open_case(targets=(13, 4), missing=((13, 5), (4, 14)))
+    w = synthetic.weights(batch["T"], 16)
+    ssel = np.array([13, 4, 0, 5], np.int32)
+    gM, gX = oracle.batched_backward(batch, M, X, w, ssel=ssel, full=True)
+    h = 1e-30
+    cells = [(13, 7), (13, 300), (4, 511), (0, 100), (5, 3)]
+    scale = np.abs(gX).max()
+    for n, (sg, cc) in enumerate(cells):
+        k = n % 3
+        Xim = np.zeros_like(X)
+        Xim[k, sg * SUB3 + cc] = h
+        Lre, Lim = oracle.batched_forward_cs(batch, M, X, Xim, full=True)
+        d = float(np.sum(w * Lim)) / h
+        col = list(ssel).index(sg) * SUB3 + cc
+        assert abs(gX[k, col] - d) <= 1e-12 * scale + 1e-11 * abs(d), (sg, cc, k, gX[k, col], d)
+    # the complex forward's real part is the real forward
+    Lf = oracle.batched_forward(batch, M, X, full=True)
+    assert np.allclose(Lre, Lf, rtol=1e-14, atol=1e-14 * np.abs(Lf).max())
+
+
+def test_full_position_gradient_central_difference():
+    batch, M, X = small_open_case(targets=(13,), missing=())
+    w = synthetic.weights(batch["T"], 17)
+    ssel = np.array([13, 12], np.int32)
+    gM, gX = oracle.batched_backward(batch, M, X, w, ssel=ssel, full=True)
+    eps = 1e-6
+    for q, (sg, cc, k) in enumerate([(13, 77, 0), (12, 5, 2)]):
+        c = sg * SUB3 + cc
+        Xp = X.copy()
+        Xm = X.copy()
+        Xp[k, c] += eps
+        Xm[k, c] -= eps
+        d = (_loss_full(batch, M, Xp, w) - _loss_full(batch, M, Xm, w)) / (2 * eps)
+        assert abs(gX[k, q * SUB3 + cc] - d) <= 1e-6 * np.abs(gX).max()
+
+
+def test_full_position_gradients_sum_to_zero():
+    batch, M, X = small_open_case(targets=(13,), missing=((13, 5),))
+    w = synthetic.weights(batch["T"], 19)
+    gM, gX = oracle.batched_backward(batch, M, X, w, full=True)
+    assert np.all(np.abs(gX.sum(axis=1)) <= 1e-12 * np.abs(gX).sum(axis=1))
