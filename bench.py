@@ -211,7 +211,8 @@ def main():
     # ------------------------------------ forward with the full truncation
     full = None
     if args.full_steps > 0:
-        full = full_truncation(plan, pairs, args.full_steps, Md, Xd, L, ot, torch, args.full_sched)
+        full = full_truncation(plan, pairs, args.full_steps, Md, Xd, L, ot, torch, args.full_sched,
+                               wd, gM, gX)
 
     # ------------------------------------------------- a two-level FMM step
     two_level = None
@@ -385,12 +386,18 @@ def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev, plan=None, b
 # the hardware peak), so the roofline uses the reduced count.
 FULL_FLOP_REDUCED = 756
 FULL_FLOP_PLAIN = 1264
+# its adjoint (derivatives to order 7), counted the same way for the reduced
+# formulas: r, 1/r and D_0..D_7: 23; the derivative recursion over the 85 (84)
+# derivatives the contraction reads: 330; the reduced products: 25 x 16
+# (24 x 16) -> source-role pass 1153, target-role pass 1121
+FULL_ADJ_FLOP_REDUCED = 1153 + 1121
 
 
-def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None):
+def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None, wd=None, gM=None, gX=None):
     """Times the full-truncation forward on the benchmark plan: the given
     schedule, or the fastest of three over one launch each, then `steps`
-    timed launches (HIP events on the launch stream)."""
+    timed launches (HIP events on the launch stream); with weights and
+    gradient arrays also its adjoint (both passes, 8 wavefronts each)."""
     stream = torch.cuda.current_stream()
 
     def timed(sched, n):
@@ -413,11 +420,30 @@ def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None):
     tf = pairs * FULL_FLOP_REDUCED / (ms * 1e-3) / 1e12
     log("full truncation %s: %.2f ms, %.3e pairs/s, %.2f TFLOP/s (reduced count)"
         % (cands[best], ms, pairs / (ms * 1e-3), tf))
-    return {"schedule": cands[best], "mean_ms": round(ms, 3), "pairs": pairs,
-            "pairs_per_s": pairs / (ms * 1e-3),
-            "flop_per_pair": FULL_FLOP_REDUCED, "flop_per_pair_plain": FULL_FLOP_PLAIN,
-            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)}}
+    out = {"schedule": cands[best], "mean_ms": round(ms, 3), "pairs": pairs,
+           "pairs_per_s": pairs / (ms * 1e-3),
+           "flop_per_pair": FULL_FLOP_REDUCED, "flop_per_pair_plain": FULL_FLOP_PLAIN,
+           "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)}}
+    if wd is not None and steps > 0:
+        plan.multipole_backward_full(Md, Xd, wd, gM, gX)  # warm-up
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.multipole_backward_full(Md, Xd, wd, gM, gX)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1) / steps
+        btf = pairs * FULL_ADJ_FLOP_REDUCED / (bms * 1e-3) / 1e12
+        log("full truncation adjoint: %.2f ms, %.2f TFLOP/s (reduced count); fwd+bwd %.3e pairs/s"
+            % (bms, btf, pairs / ((ms + bms) * 1e-3)))
+        out["adjoint"] = {"mean_ms": round(bms, 3), "flop_per_pair": FULL_ADJ_FLOP_REDUCED,
+                          "roofline": {"bound": "alu", "achieved": round(btf, 3), "peak": PEAK_FP64_TFLOPS,
+                                       "unit": "TFLOP/s", "frac": round(btf / PEAK_FP64_TFLOPS, 4)}}
+        out["fwd_bwd_pairs_per_s"] = pairs / ((ms + bms) * 1e-3)
+    return out
 
 
 def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torch, dev):

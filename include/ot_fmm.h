@@ -201,6 +201,14 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
 int ot_fmm_multipole_batched_full(ot_fmm_plan plan, const double* M, const double* com, double* L,
                                   int sched, void* stream);
 
+/* Adjoint of ot_fmm_multipole_batched_full (derivatives of G to order 7):
+ * the same arrays, overwrite rules and errors as ot_fmm_multipole_backward;
+ * schedules as there, AUTO = 8 wavefronts for both passes, a target-role
+ * shape of 16 wavefronts is EINVAL. */
+int ot_fmm_multipole_backward_full(ot_fmm_plan plan, const double* M, const double* com,
+                                   const double* gL, double* gM, double* gcom, int sched,
+                                   void* stream);
+
 /* Adjoint of the batched forward for the loss l = sum gL * L:
  *   gL[20][T*512] -> gM[20][S*512] = dl/dM, gcom[3][S*512] = dl/dcom.
  * gM and gcom are OVERWRITTEN; cells of store sub-grids that no target

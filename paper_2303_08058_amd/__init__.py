@@ -69,6 +69,8 @@ _lib.ot_fmm_plan_pairs.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
 _lib.ot_fmm_plan_pairs.restype = _I
 _lib.ot_fmm_multipole_batched_full.argtypes = [_P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_batched_full.restype = _I
+_lib.ot_fmm_multipole_backward_full.argtypes = [_P, _P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_backward_full.restype = _I
 _lib.ot_fmm_plan_set_coarse.argtypes = [_P, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64)]
 _lib.ot_fmm_plan_set_coarse.restype = _I
 _lib.ot_fmm_coarse_fine.argtypes = [_P, _P, _P, _P, _P, _P]
@@ -308,6 +310,15 @@ class Plan:
             "ot_fmm_multipole_backward")
         return gM, gcom
 
+    def multipole_backward_full(self, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
+        """Adjoint of multipole_batched_full (gM, gcom overwritten)."""
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_backward_full(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(gL, sl, "gL"),
+            _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"), int(sched), _stream(stream)),
+            "ot_fmm_multipole_backward_full")
+        return gM, gcom
+
     def autotune(self, M, com, L, gL=None, gM=None, gcom=None, stream=None):
         sm, sx, sl = self._shapes()
         f = ctypes.c_int()
@@ -354,6 +365,10 @@ def ot_fmm_multipole_batched_full(plan, M, com, L, sched=SCHED_AUTO, stream=None
     return plan.multipole_batched_full(M, com, L, sched, stream)
 
 
+def ot_fmm_multipole_backward_full(plan, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_backward_full(M, com, gL, gM, gcom, sched, stream)
+
+
 def ot_fmm_plan_set_coarse(plan, Sp, coarse, octant):
     return plan.set_coarse(Sp, coarse, octant)
 
@@ -363,18 +378,23 @@ def ot_fmm_coarse_fine(plan, com, Mp, comp, L, stream=None):
 
 
 class MultipoleBatched(torch.autograd.Function):
-    """L = multipole_batched(M, com) with the hand-written adjoint as backward.
+    """L = multipole_batched(M, com) with the hand-written adjoint as backward
+    (full=True: the full truncation and its adjoint).
 
-    Usage: L = MultipoleBatched.apply(M, com, plan)."""
+    Usage: L = MultipoleBatched.apply(M, com, plan[, full])."""
 
     @staticmethod
-    def forward(ctx, M, com, plan):
+    def forward(ctx, M, com, plan, full=False):
         M = M.contiguous()
         com = com.contiguous()
         L = torch.empty((20, plan.T * 512), dtype=torch.float64, device=M.device)
-        plan.multipole_batched(M, com, L)
+        if full:
+            plan.multipole_batched_full(M, com, L)
+        else:
+            plan.multipole_batched(M, com, L)
         ctx.save_for_backward(M, com)
         ctx.plan = plan
+        ctx.full = bool(full)
         return L
 
     @staticmethod
@@ -383,13 +403,16 @@ class MultipoleBatched(torch.autograd.Function):
         gL = gL.contiguous()
         gM = torch.empty_like(M)
         gcom = torch.empty_like(com)
-        ctx.plan.multipole_backward(M, com, gL, gM, gcom)
-        return gM, gcom, None
+        if ctx.full:
+            ctx.plan.multipole_backward_full(M, com, gL, gM, gcom)
+        else:
+            ctx.plan.multipole_backward(M, com, gL, gM, gcom)
+        return gM, gcom, None, None
 
 
-def multipole(M, com, plan):
+def multipole(M, com, plan, full=False):
     """Differentiable batched multipole interaction (see MultipoleBatched)."""
-    return MultipoleBatched.apply(M, com, plan)
+    return MultipoleBatched.apply(M, com, plan, full)
 
 
 # ---------------------------------------------------------------------------

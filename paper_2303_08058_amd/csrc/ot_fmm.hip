@@ -305,16 +305,27 @@ int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
     return fail(OT_FMM_EINVAL, "unknown forward schedule");
 }
 
-int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
-                double* gM, double* gcom, int sched, hipStream_t stream)
+// Adjoint of the batched forward (FULL: of the full truncation, with
+// derivatives to order 7; 8 wavefronts by default, 16 refused -- their
+// register budget is far below what the order-7 sums hold -- and not timed
+// by the plan's events).
+template <bool FULL>
+int bwd_any(ot_fmm_plan plan, const double* M, const double* com, const double* gL, double* gM,
+            double* gcom, int sched, hipStream_t stream)
 {
+    constexpr int kB2 = FULL ? MODE_B2F_STORE : MODE_B2_STORE;
+    constexpr int kB1 = FULL ? MODE_B1F_STORE : MODE_B1_STORE;
+    const int w2 = FULL ? -1 : 1, w1 = FULL ? -1 : 2;
     // target-role schedule in the low byte, source-role schedule in the next
     int tsched = sched & 0xff, ssched = (sched >> 8) & 0xff;
     if (tsched == OT_FMM_SCHED_AUTO)
-        tsched = (plan->tuned_bwd & 0xff) ? (plan->tuned_bwd & 0xff) : OT_FMM_SCHED_W16;
+        tsched = FULL ? OT_FMM_SCHED_W8
+                      : ((plan->tuned_bwd & 0xff) ? (plan->tuned_bwd & 0xff) : OT_FMM_SCHED_W16);
     if (ssched == OT_FMM_SCHED_AUTO)
-        ssched = (plan->tuned_bwd >> 8) ? (plan->tuned_bwd >> 8) : kDefaultSourceSched;
+        ssched = FULL ? OT_FMM_SCHED_W8 : ((plan->tuned_bwd >> 8) ? (plan->tuned_bwd >> 8) : kDefaultSourceSched);
     if (!valid_bwd_sched(tsched | (ssched << 8))) return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    if (FULL && (tsched & kShapeMask) == OT_FMM_SCHED_W16)
+        return fail(OT_FMM_EINVAL, "16 wavefronts are not available for the full truncation's adjoint");
     const long NS = (long)plan->S * kSub3, NT = (long)plan->T * kSub3;
     // source role: owners are store sub-grids, sources the target cells that see them
     KParams b2{};
@@ -337,8 +348,8 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     const bool spers = (ssched & OT_FMM_SCHED_PERSISTENT) != 0;
     if (ssched & OT_FMM_SCHED_LOCAL) b2.order = plan->d_rev_local;
     int rc = (ssched & kShapeMask) == OT_FMM_SCHED_W8P2
-                 ? launch_timed<MODE_B2_STORE, 8, 2>(plan, 1, b2, plan->S, spers, stream)
-                 : launch_timed<MODE_B2_STORE, 8>(plan, 1, b2, plan->S, spers, stream);
+                 ? launch_timed<kB2, 8, 2>(plan, w2, b2, plan->S, spers, stream)
+                 : launch_timed<kB2, 8>(plan, w2, b2, plan->S, spers, stream);
     if (rc) return rc;
     // target role: owners are targets, sources their neighbours' cells
     KParams b1{};
@@ -358,11 +369,16 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     const bool tpers = (tsched & OT_FMM_SCHED_PERSISTENT) != 0;
     if (tsched & OT_FMM_SCHED_LOCAL) b1.order = plan->d_fwd_local;
     const int tshape = tsched & kShapeMask;
-    if (tshape == OT_FMM_SCHED_W16)
-        return launch_timed<MODE_B1_STORE, 16>(plan, 2, b1, plan->T, tpers, stream);
-    if (tshape == OT_FMM_SCHED_W8P2)
-        return launch_timed<MODE_B1_STORE, 8, 2>(plan, 2, b1, plan->T, tpers, stream);
-    return launch_timed<MODE_B1_STORE, 8>(plan, 2, b1, plan->T, tpers, stream);
+    if constexpr (!FULL)
+        if (tshape == OT_FMM_SCHED_W16) return launch_timed<kB1, 16>(plan, w1, b1, plan->T, tpers, stream);
+    if (tshape == OT_FMM_SCHED_W8P2) return launch_timed<kB1, 8, 2>(plan, w1, b1, plan->T, tpers, stream);
+    return launch_timed<kB1, 8>(plan, w1, b1, plan->T, tpers, stream);
+}
+
+int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL, double* gM,
+                double* gcom, int sched, hipStream_t stream)
+{
+    return bwd_any<false>(plan, M, com, gL, gM, gcom, sched, stream);
 }
 
 int check_plan(ot_fmm_plan plan)
@@ -1012,6 +1028,28 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
     }
     if (!valid_bwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown backward schedule");
     return bwd_batched(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole_backward_full(ot_fmm_plan plan, const double* M, const double* com,
+                                   const double* gL, double* gM, double* gcom, int sched,
+                                   void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(gM) || !aligned16(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    {
+        const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+        const double* in[3] = {M, com, gL};
+        const int64_t nin[3] = {20 * NS, 3 * NS, 20 * NT};
+        for (int i = 0; i < 3; ++i)
+            if (overlap(gM, 20 * NS, in[i], nin[i]) || overlap(gcom, 3 * NS, in[i], nin[i]))
+                return fail(OT_FMM_EINVAL, "outputs overlap inputs");
+        if (overlap(gM, 20 * NS, gcom, 3 * NS)) return fail(OT_FMM_EINVAL, "gM overlaps gcom");
+    }
+    if (!valid_bwd_sched(sched)) return fail(OT_FMM_EINVAL, "unknown backward schedule");
+    return bwd_any<true>(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
 }
 
 int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double* L,

@@ -371,7 +371,8 @@ __device__ __forceinline__ void expand(const double* acc, double* full, std::int
 // keeps complete source shells of orders 2 and 3, and the three outputs
 // L_{g+xx}, L_{g+yy}, L_{g+zz} keep the same sources.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void radial6(double x, double y, double z, double* D)
+template <int N>
+__device__ __forceinline__ void radial(double x, double y, double z, double* D)
 {
     const double r2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
     const double ri = rsqrt_fp64(r2);
@@ -379,7 +380,7 @@ __device__ __forceinline__ void radial6(double x, double y, double z, double* D)
     D[0] = -ri;
     D[1] = ri * ri2;
 #pragma unroll
-    for (int p = 1; p < 6; ++p) D[p + 1] = (-(2.0 * p + 1.0)) * D[p] * ri2;
+    for (int p = 1; p < N; ++p) D[p + 1] = (-(2.0 * p + 1.0)) * D[p] * ri2;
 }
 
 template <int P, int A, int B, int C>
@@ -402,28 +403,29 @@ __device__ __forceinline__ double phi(const double* r, const double* D)
     }
 }
 
-// acc[kept slot of g] += sum_b q[b] G_{g + kRedP[b]} over all 16 reduced sources
-template <int G_, int B>
+// acc[kept slot of g in [LO, ...)] += sum_b q[b] G_{g + kRedP[b]} over all 16
+// reduced sources
+template <int LO, int G_, int B>
 __device__ __forceinline__ void term_full(double* acc, const double* q, const double* r, const double* D)
 {
     if constexpr (kept(G_)) {
-        constexpr int slot = kept_slot(0, G_);
+        constexpr int slot = kept_slot(LO, G_);
         constexpr Exp3 e = exp_of(G_);
         constexpr Exp3 f = exp_of(kRedP[B]);
         acc[slot] = __builtin_fma(q[B], phi<0, e.a + f.a, e.b + f.b, e.c + f.c>(r, D), acc[slot]);
     }
 }
-template <int G_, int... B>
+template <int LO, int G_, int... B>
 __device__ __forceinline__ void row_full(double* acc, const double* q, const double* r, const double* D,
                                          std::integer_sequence<int, B...>)
 {
-    (term_full<G_, B>(acc, q, r, D), ...);
+    (term_full<LO, G_, B>(acc, q, r, D), ...);
 }
-template <int... I>
+template <int LO, int... I>
 __device__ __forceinline__ void contract_full(double* acc, const double* q, const double* r, const double* D,
                                               std::integer_sequence<int, I...>)
 {
-    (row_full<I>(acc, q, r, D, std::make_integer_sequence<int, kNRed>{}), ...);
+    (row_full<LO, LO + I>(acc, q, r, D, std::make_integer_sequence<int, kNRed>{}), ...);
 }
 
 // Adjoint epilogue: with C_g (g = 1..34, stored at C[g - 1]) the derivative
@@ -474,7 +476,9 @@ enum Mode : int {
     MODE_FWD_STORE = 2,  // batched forward -> L
     MODE_B2_STORE = 3,   // adjoint, source role per store sub-grid -> gM, gX (overwrite)
     MODE_B1_STORE = 4,   // adjoint, target role per target -> gX (accumulate)
-    MODE_FULL_STORE = 5  // batched forward, full truncation -> L
+    MODE_FULL_STORE = 5,  // batched forward, full truncation -> L
+    MODE_B2F_STORE = 6,   // adjoint of the full truncation, source role -> gM, gX (overwrite)
+    MODE_B1F_STORE = 7    // adjoint of the full truncation, target role -> gX (accumulate)
 };
 
 struct KParams {
@@ -502,13 +506,17 @@ struct ModeTraits {
     // staged source components: the mass, or the 16 trace-reduced moments
     static constexpr int nq = (MODE == MODE_MONO_HALO) ? 1 : kNRed;
     static constexpr int nc = nq + 3;  // + centre of mass
-    static constexpr bool adjoint = (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE);
+    static constexpr bool adjoint =
+        (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE || MODE == MODE_B1F_STORE || MODE == MODE_B2F_STORE);
+    static constexpr bool source_role = (MODE == MODE_B2_STORE || MODE == MODE_B2F_STORE);
     // accumulators: monopole 20; forward 16 kept of 20; target-role adjoint
-    // 24 kept of the 34 orders 1..4; source-role adjoint 16 + 24
-    static constexpr int nacc = (MODE == MODE_MONO_HALO)  ? 20
-                                : (MODE == MODE_B1_STORE) ? 24
-                                : (MODE == MODE_B2_STORE) ? 40
-                                                          : 16;
+    // 24 kept of the 34 orders 1..4; source-role adjoint 16 + 24; with the
+    // full truncation the source role keeps one set for orders 0..4 (25)
+    static constexpr int nacc = (MODE == MODE_MONO_HALO)                             ? 20
+                                : (MODE == MODE_B1_STORE || MODE == MODE_B1F_STORE) ? 24
+                                : (MODE == MODE_B2_STORE)                           ? 40
+                                : (MODE == MODE_B2F_STORE)                          ? 25
+                                                                                    : 16;
 };
 
 // LDS plane layout: cell-major, Layout::stride doubles per cell -- the
@@ -572,7 +580,7 @@ __device__ __forceinline__ Chunk<MODE> chunk_of(const KParams& p, const int4* re
     const int cS = c_red_src[rb][1];
     const int cS2 = cS >= 0 ? cS : cP;
     const int cx = isx ? c : 0;
-    const double* sc = (MODE == MODE_B2_STORE) ? c_scale_rev : c_scale_fwd;
+    const double* sc = T::source_role ? c_scale_rev : c_scale_fwd;
     Chunk<MODE> ch;
     long off, stride_c;
     const double* base;
@@ -796,9 +804,21 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
                     } else if constexpr (MODE == MODE_FULL_STORE) {
                         // L_a, |a| <= 3 and |b| <= 3
                         double D[7];
-                        radial6(rx, ry, rz, D);
+                        radial<6>(rx, ry, rz, D);
                         const double rr[3] = {rx, ry, rz};
-                        contract_full(acc, q, rr, D, std::make_integer_sequence<int, 20>{});
+                        contract_full<0>(acc, q, rr, D, std::make_integer_sequence<int, 20>{});
+                    } else if constexpr (MODE == MODE_B1F_STORE) {
+                        // L'_g, 1 <= |g| <= 4, every |b| <= 3
+                        double D[8];
+                        radial<7>(rx, ry, rz, D);
+                        const double rr[3] = {rx, ry, rz};
+                        contract_full<1>(acc, q, rr, D, std::make_integer_sequence<int, 34>{});
+                    } else if constexpr (MODE == MODE_B2F_STORE) {
+                        // C_d, 0 <= |d| <= 4, every |a| <= 3
+                        double D[8];
+                        radial<7>(rx, ry, rz, D);
+                        const double rr[3] = {rx, ry, rz};
+                        contract_full<0>(acc, q, rr, D, std::make_integer_sequence<int, 35>{});
                     } else if constexpr (!T::adjoint) {
                         // L_a, |a| + |b| <= 3
                         double G[20];
@@ -872,8 +892,12 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     } else {
         double C[34];
         double F[20];
-        if constexpr (MODE == MODE_B1_STORE) {
+        if constexpr (MODE == MODE_B1_STORE || MODE == MODE_B1F_STORE) {
             expand<1>(acc, C, std::make_integer_sequence<int, 34>{});
+        } else if constexpr (MODE == MODE_B2F_STORE) {
+            // one set of sums for orders 0..4: F (orders 0..3) and C (1..4)
+            expand<0>(acc, F, std::make_integer_sequence<int, 20>{});
+            expand<1>(acc + 1, C, std::make_integer_sequence<int, 34>{});
         } else {
             double E[34];
             expand<0>(acc, F, std::make_integer_sequence<int, 20>{});
@@ -884,13 +908,13 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         double c[20];
 #pragma unroll
         for (int a = 0; a < 20; ++a) c[a] = p.aux[a * p.aux_stride + ab];
-        if constexpr (MODE == MODE_B2_STORE)
+        if constexpr (T::source_role)
             scale_inv_fact(c, std::make_integer_sequence<int, 20>{});  // M_b / b!
         double gx[3] = {0.0, 0.0, 0.0};
         grad_x(c, C, gx, std::make_integer_sequence<int, 20>{});
         const long b = p.out_blk ? p.out_blk[owner] : owner;
         const long ob = b * kSub3 + cell;
-        if constexpr (MODE == MODE_B2_STORE) {
+        if constexpr (T::source_role) {
             scale_inv_fact(F, std::make_integer_sequence<int, 20>{});  // gM_b = F_b / b!
 #pragma unroll
             for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = F[a];

@@ -117,3 +117,74 @@ def test_full_rejects_bad_arguments(ot):
                                             ctypes.c_void_p(dX.data_ptr()),
                                             ctypes.c_void_p(dM.data_ptr() + 8 * 512), 0, None)
     assert rc == ot.OT_FMM_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# adjoint of the full truncation
+# ---------------------------------------------------------------------------
+# target role | source role << 8: 1 W8, 3 W8P2, 0x10 persistent, 0x20 XCD-local
+@pytest.fixture(scope="module")
+def small_adjoint_case():
+    batch, M, X = synthetic.batched_config(2, 26, missing_frac=0.5)
+    w = synthetic.weights(batch["T"], 27)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, full=True)
+    return batch, M, X, w, gM_ref, gX_ref
+
+
+@pytest.mark.parametrize("sched", [0, 0x0101, 0x0303, 0x2111, 0x1121])
+def test_full_adjoint_small_periodic_with_missing(ot, small_adjoint_case, sched):
+    batch, M, X, w, gM_ref, gX_ref = small_adjoint_case
+    plan = ot.Plan.from_batch(batch)
+    NS = batch["S"] * SUB3
+    gM, gX = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_full(_dev(M), _dev(X), _dev(w), gM, gX, sched=sched)
+    print("full adjoint gM", assert_parity(_host(gM), gM_ref, TOL, what="full gM"))
+    print("full adjoint gX", assert_parity(_host(gX), gX_ref, TOL, what="full gX"))
+    gM2, gX2 = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_full(_dev(M), _dev(X), _dev(w), gM2, gX2, sched=sched)
+    assert np.array_equal(_host(gM2), _host(gM)) and np.array_equal(_host(gX2), _host(gX))
+
+
+def test_full_adjoint_open_lattice_and_autograd(ot):
+    """Open 3^3 lattice, every sub-grid a target: the autograd function with
+    full=True gives the oracle's gradients of sum(w * L_full)."""
+    import torch
+    batch, M, X = synthetic.batched_config(3, 28, periodic=False)
+    w = synthetic.weights(batch["T"], 29)
+    sel = np.array([0, 13, 26], np.int32)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=sel, full=True)
+    plan = ot.Plan.from_batch(batch)
+    Mt = _dev(M).requires_grad_(True)
+    Xt = _dev(X).requires_grad_(True)
+    L = ot.multipole(Mt, Xt, plan, full=True)
+    (L * _dev(w)).sum().backward()
+    cols = lambda a: a.reshape(a.shape[0], -1, SUB3)[:, sel].reshape(a.shape[0], -1)
+    assert_parity(cols(_host(Mt.grad)), gM_ref, TOL, what="autograd full gM")
+    assert_parity(cols(_host(Xt.grad)), gX_ref, TOL, what="autograd full gX")
+    ref_L = oracle.batched_forward(batch, M, X, tsel=sel, full=True)
+    assert_parity(cols(_host(L.detach())), ref_L, TOL, what="autograd full L")
+
+
+def test_full_adjoint_config4_sampled(ot):
+    """8^3 sub-grids, open boundary, w ~ N(0, 1): sampled store sub-grids."""
+    batch, M, X = synthetic.config4()
+    w = synthetic.weights(batch["T"], 2004)
+    plan = ot.Plan.from_batch(batch)
+    NS = batch["S"] * SUB3
+    gM, gX = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_full(_dev(M), _dev(X), _dev(w), gM, gX)
+    sel = np.array([0, 63, 200, 273, 511], np.int32)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=sel, full=True)
+    cols = lambda a: a.reshape(a.shape[0], -1, SUB3)[:, sel].reshape(a.shape[0], -1)
+    print("config4 full gM", assert_parity(cols(_host(gM)), gM_ref, TOL, what="config4 full gM"))
+    print("config4 full gX", assert_parity(cols(_host(gX)), gX_ref, TOL, what="config4 full gX"))
+
+
+def test_full_adjoint_rejects_16_wavefronts(ot):
+    batch, M, X = synthetic.batched_config(2, 30)
+    plan = ot.Plan.from_batch(batch)
+    w = synthetic.weights(batch["T"], 31)
+    NS = batch["S"] * SUB3
+    with pytest.raises(ot.OtFmmError) as e:
+        plan.multipole_backward_full(_dev(M), _dev(X), _dev(w), _empty(20, NS), _empty(3, NS), sched=0x0102)
+    assert e.value.code == ot.OT_FMM_EINVAL
