@@ -188,3 +188,36 @@ def test_full_adjoint_rejects_16_wavefronts(ot):
     with pytest.raises(ot.OtFmmError) as e:
         plan.multipole_backward_full(_dev(M), _dev(X), _dev(w), _empty(20, NS), _empty(3, NS), sched=0x0102)
     assert e.value.code == ot.OT_FMM_EINVAL
+
+
+@pytest.mark.parametrize("fsched,bsched", [(1, 0x0101), (0x11, 0x1111)])
+def test_full_caller_captured_graph_replays(ot, fsched, bsched):
+    """The full forward and its adjoint captured into a caller's graph
+    (torch.cuda.CUDAGraph) replay bit for bit like the eager launches,
+    several times with eager work in between (persistent forms record their
+    counter resets as kernel nodes)."""
+    import torch
+    batch, M, X = synthetic.batched_config(3, 97, missing_frac=0.3)
+    w = synthetic.weights(batch["T"], 98)
+    plan = ot.Plan.from_batch(batch)
+    NS, NT = batch["S"] * SUB3, batch["T"] * SUB3
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    refL, refM, refX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
+    plan.multipole_batched_full(Md, Xd, refL, sched=fsched)
+    plan.multipole_backward_full(Md, Xd, wd, refM, refX, sched=bsched)
+    L, gM, gX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.multipole_batched_full(Md, Xd, L, sched=fsched, stream=s)
+        plan.multipole_backward_full(Md, Xd, wd, gM, gX, sched=bsched, stream=s)
+    for rep in range(3):
+        for t in (L, gM, gX):
+            t.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(L, refL) and torch.equal(gM, refM) and torch.equal(gX, refX), rep
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        del junk
