@@ -67,8 +67,9 @@ def _load():
               lib.orc_batched_backward, lib.orc_batched_backward_full):
         f.argtypes = [i, i, P, P, P, P, P, P, P, P, i, P, P, i]
         f.restype = i
-    lib.orc_coarse_fine.argtypes = [i, i, P, P, P, P, P, i, P, P, P, P, P, i, P, P, i]
-    lib.orc_coarse_fine.restype = i
+    for f in (lib.orc_coarse_fine, lib.orc_coarse_fine_full):
+        f.argtypes = [i, i, P, P, P, P, P, i, P, P, P, P, P, i, P, P, i]
+        f.restype = i
     lib.orc_m2m.argtypes = [i, i, P, P, P, P, i, P, P, i]
     lib.orc_m2m.restype = i
     lib.orc_l2l.argtypes = [i, i, P, P, P, P, P, i]
@@ -211,10 +212,10 @@ def batched_backward(batch, M, X, gL, ssel=None, nthreads: int = 0, full: bool =
 
 
 def coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=None, want_abs: bool = False,
-                nthreads: int = 0):
+                nthreads: int = 0, full: bool = False):
     """Coarse contributions (20, nsel*512) for missing neighbours that have a
     coarse substitute: coarse / octant (T, 27), -1 where none; Mp, Xp the
-    coarse store."""
+    coarse store. full=True: the full truncation (every |b| <= 3)."""
     S, T, tgt, nbr, shift, period = _batch_args(batch)
     tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
     X = _f64(X)
@@ -225,9 +226,10 @@ def coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=None, want_abs: bool = Fa
     octant = np.ascontiguousarray(octant, dtype=np.int8).reshape(T, 27)
     L = np.zeros((NM, len(tsel) * SUB3), np.float64)
     A = np.zeros_like(L) if want_abs else None
-    rc = _load().orc_coarse_fine(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(X), Sp,
-                                 _ptr(coarse), _ptr(octant), _ptr(Mp), _ptr(Xp), _ptr(tsel), len(tsel),
-                                 _ptr(L), _ptr(A), nthreads)
+    fn = _load().orc_coarse_fine_full if full else _load().orc_coarse_fine
+    rc = fn(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(X), Sp,
+            _ptr(coarse), _ptr(octant), _ptr(Mp), _ptr(Xp), _ptr(tsel), len(tsel),
+            _ptr(L), _ptr(A), nthreads)
     if rc:
         raise ValueError("orc_coarse_fine rejected its arguments")
     return (L, A) if want_abs else L

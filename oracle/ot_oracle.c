@@ -484,13 +484,17 @@ int orc_batched_forward_full(int S, int T, const int32_t *tgt, const int32_t *nb
  * A J with some child near i is left out, like every near pair.
  * Mp[20][Sp*512], Xp[3][Sp*512]: coarse store; coarse cell (cx, cy, cz) of
  * octant o is cell (cx + 4 o_x) + 8 (cy + 4 o_y) + 64 (cz + 4 o_z) of P.
- * Returns the coarse contributions only, L (20, nsel*512), for targets tsel. */
-int orc_coarse_fine(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
-                    const double *period, const double *X, int Sp, const int32_t *coarse,
-                    const int8_t *octant, const double *Mp, const double *Xp,
-                    const int32_t *tsel, int nsel, double *L, double *Aabs, int nthreads)
+ * Returns the coarse contributions only, L (20, nsel*512), for targets tsel.
+ * full != 0: the same substitute under the full truncation (every |b| <= 3
+ * for every |a| <= 3), as in the full batched forward. */
+static int coarse_fine(int full, int S, int T, const int32_t *tgt, const int32_t *nbr,
+                       const int8_t *shift, const double *period, const double *X, int Sp,
+                       const int32_t *coarse, const int8_t *octant, const double *Mp,
+                       const double *Xp, const int32_t *tsel, int nsel, double *L,
+                       double *Aabs, int nthreads)
 {
     init_tables();
+    init_tables6();
     if (check_batch(S, T, tgt, nbr) || Sp <= 0 || !coarse || !octant) return -1;
     for (int t = 0; t < T; ++t)
         for (int s = 0; s < 27; ++s) {
@@ -535,7 +539,7 @@ int orc_coarse_fine(int S, int T, const int32_t *tgt, const int32_t *nbr, const 
                     double Xj[3] = {Xp[jidx] + sh[0], Xp[NP + jidx] + sh[1], Xp[2 * NP + jidx] + sh[2]};
                     double Mj[NM];
                     for (int b = 0; b < NM; ++b) Mj[b] = Mp[b * NP + jidx];
-                    pair_forward_re(Xi, Xj, Mj, NM, 3, acc, Aabs ? aabs : NULL);
+                    pair_forward_any(full, Xi, Xj, Mj, NM, 3, acc, Aabs ? aabs : NULL);
                 }
             }
             for (int a = 0; a < NM; ++a) {
@@ -544,6 +548,25 @@ int orc_coarse_fine(int S, int T, const int32_t *tgt, const int32_t *nbr, const 
             }
         }
     return 0;
+}
+
+int orc_coarse_fine(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
+                    const double *period, const double *X, int Sp, const int32_t *coarse,
+                    const int8_t *octant, const double *Mp, const double *Xp,
+                    const int32_t *tsel, int nsel, double *L, double *Aabs, int nthreads)
+{
+    return coarse_fine(0, S, T, tgt, nbr, shift, period, X, Sp, coarse, octant, Mp, Xp, tsel, nsel,
+                       L, Aabs, nthreads);
+}
+
+int orc_coarse_fine_full(int S, int T, const int32_t *tgt, const int32_t *nbr,
+                         const int8_t *shift, const double *period, const double *X, int Sp,
+                         const int32_t *coarse, const int8_t *octant, const double *Mp,
+                         const double *Xp, const int32_t *tsel, int nsel, double *L,
+                         double *Aabs, int nthreads)
+{
+    return coarse_fine(1, S, T, tgt, nbr, shift, period, X, Sp, coarse, octant, Mp, Xp, tsel, nsel,
+                       L, Aabs, nthreads);
 }
 
 /* Same sum with complex centres of mass X = Xre + i Xim (moments real), for

@@ -115,13 +115,15 @@ def _fine_reference(batch, M, X, t, ci, coarse):
     return L[:, ci], included
 
 
-@pytest.mark.parametrize("periodic", [False, True])
-def test_coincident_children_equal_their_coarse_cell(periodic):
+@pytest.mark.parametrize("periodic,full", [(False, False), (True, False), (True, True)])
+def test_coincident_children_equal_their_coarse_cell(periodic, full):
+    """Point masses at one point: the coarse cell carries the mass alone, so
+    both truncations give the fine sum up to rounding."""
     batch, coarse, octant = _case(periodic)
     M, X = _store(0.0)
     Mp, Xp = oracle.m2m(synthetic.octree_children(N), M, X)
     ts = [t for t in range(batch["T"]) if (coarse[t] >= 0).any()][:3]
-    got, A = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=ts, want_abs=True)
+    got, A = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=ts, want_abs=True, full=full)
     rng = np.random.default_rng(5)
     for q, t in enumerate(ts):
         for ci in rng.choice(SUB3, 4, replace=False):
@@ -131,7 +133,12 @@ def test_coincident_children_equal_their_coarse_cell(periodic):
             assert np.all(np.abs(got[:, col] - ref) <= 1e-13 * A[:, col]), (t, ci)
 
 
-def test_spread_children_converge_at_the_truncation_order():
+@pytest.mark.parametrize("full", [False, True])
+def test_spread_children_converge_at_the_truncation_order(full):
+    """Children spread by a: the coarse moments of order k grow like a^k. The
+    total-order substitute drops moments of order 4 - n from the outputs of
+    order n (error ~ a^(4-n)); the full one keeps every moment up to order 3
+    in every output (error ~ a^4 in all of them)."""
     batch, coarse, octant = _case(False, seed=73)
     t = next(t for t in range(batch["T"]) if (coarse[t] >= 0).sum() >= 2)
     M, X = _store(0.1)
@@ -140,13 +147,17 @@ def test_spread_children_converge_at_the_truncation_order():
     for a in (0.2, 0.1, 0.05):
         M, X = _store(a)
         Mp, Xp = oracle.m2m(synthetic.octree_children(N), M, X)
-        got = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=[t])[:, ci]
+        got = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=[t], full=full)[:, ci]
         ref, _ = _fine_reference(batch, M, X, t, ci, coarse)
         errs.append(np.abs(got - ref))
     for order, comps in enumerate(([0], [1, 2, 3], list(range(4, 10)), list(range(10, 20)))):
         e = [float(np.max(x[comps])) for x in errs]
-        rate = 2.0 ** (4 - order)
+        # (the dipole about the centre of mass is zero: order-3 outputs of the
+        # total order lose the quadrupole first)
+        rate = 2.0 ** (4 if full else max(4 - order, 2))
         assert e[1] < e[0] / (0.6 * rate) and e[2] < e[1] / (0.6 * rate), (order, e)
+        # and not faster: the rate is that of the first omitted order
+        assert e[1] > e[0] / (1.6 * rate) and e[2] > e[1] / (1.6 * rate), (order, e)
 
 
 def test_arguments_are_validated():
