@@ -219,6 +219,9 @@ def main():
     if args.tree_steps > 0 and args.n % 2 == 0 and not args.no_two_level:
         two_level = two_level_step(args.n, args.tree_steps, plan, batch, fs, Md, Xd, L, ot, synthetic,
                                    np, torch, dev)
+        if args.full_steps > 0:
+            two_level["full_truncation"] = two_level_step(args.n, args.full_steps, plan, batch, fs, Md, Xd,
+                                                          L, ot, synthetic, np, torch, dev, full=True)
 
     # --------------------------------------- batched vs per-sub-grid launches
     per_sub = None
@@ -334,26 +337,27 @@ def tree_passes(n, steps, Md, Xd, L, ot, synthetic, np, torch, dev, plan=None, b
         coarse, octant = synthetic.coarse_tables(n, batch)
         cpairs = plan.set_coarse(Sp, coarse, octant)
         ntg = int((coarse >= 0).any(1).sum())
-        for _ in range(2):
-            plan.coarse_fine(Xd, Mp, Xp, L)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(steps):
-            plan.coarse_fine(Xd, Mp, Xp, L)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        tf = cpairs * FLOP_PER_PAIR["forward"] / (ms * 1e-3) / 1e12
-        out["coarse_fine"] = {
-            "mean_ms": round(ms, 4), "targets": ntg, "substituted_slots": int((coarse >= 0).sum()),
-            "pairs": cpairs, "unit": "(target cell, coarse cell) pair",
-            "flop_per_pair": FLOP_PER_PAIR["forward"],
-            "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)}}
-        log("coarse_fine     %.3f ms  %d targets, %d pairs, %.2f TFLOP/s"
-            % (ms, ntg, cpairs, tf))
+        # both truncations; the full one counted like the full forward
+        for key, full, fpp in (("coarse_fine", False, FLOP_PER_PAIR["forward"]),
+                               ("coarse_fine_full", True, FULL_FLOP_REDUCED)):
+            for _ in range(2):
+                plan.coarse_fine(Xd, Mp, Xp, L, full=full)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(steps):
+                plan.coarse_fine(Xd, Mp, Xp, L, full=full)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            tf = cpairs * fpp / (ms * 1e-3) / 1e12
+            out[key] = {
+                "mean_ms": round(ms, 4), "targets": ntg, "substituted_slots": int((coarse >= 0).sum()),
+                "pairs": cpairs, "unit": "(target cell, coarse cell) pair", "flop_per_pair": fpp,
+                "roofline": {"bound": "alu", "achieved": round(tf, 3), "peak": PEAK_FP64_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(tf / PEAK_FP64_TFLOPS, 4)}}
+            log("%-16s %.3f ms  %d targets, %d pairs, %.2f TFLOP/s" % (key, ms, ntg, cpairs, tf))
     # a plain device copy of 2 GiB on the same stream, as the attainable
     # read+write bandwidth these streaming kernels compare with
     a = torch.empty(1 << 28, **f64)
@@ -446,12 +450,14 @@ def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None, wd=Non
     return out
 
 
-def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torch, dev):
+def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torch, dev, full=False):
     """A two-level step on the benchmark store, from the library's calls in
     sequence on one stream: upward pass to the (n/2)^3 parent level, fine
     interaction plus coarse substitutes for the missing neighbours, the
     parent level's interaction, downward pass into the fine coefficients,
-    evaluation of force and energy. HIP events around the whole sequence."""
+    evaluation of force and energy. HIP events around the whole sequence.
+    full=True: the three interaction passes with the full truncation (their
+    default schedule)."""
     ch = synthetic.octree_children(n)
     Sp, S = ch.shape[0], n ** 3
     tree = ot.Tree(ch, S)
@@ -468,9 +474,15 @@ def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torc
 
     def step():
         tree.m2m(Md, Xd, Mp, Xp)
-        plan.multipole_batched(Md, Xd, L, sched=fs)
-        plan.coarse_fine(Xd, Mp, Xp, L)
-        pplan.multipole_batched(Mp, Xp, Lp)
+        if full:
+            plan.multipole_batched_full(Md, Xd, L)
+        else:
+            plan.multipole_batched(Md, Xd, L, sched=fs)
+        plan.coarse_fine(Xd, Mp, Xp, L, full=full)
+        if full:
+            pplan.multipole_batched_full(Mp, Xp, Lp)
+        else:
+            pplan.multipole_batched(Mp, Xp, Lp)
         tree.l2l(Lp, Xp, Xd, L)
         ot.ot_fmm_evaluate(Md, L, F, W)
 
@@ -487,8 +499,8 @@ def two_level_step(n, steps, plan, batch, fs, Md, Xd, L, ot, synthetic, np, torc
     ms = e0.elapsed_time(e1) / steps
     fine_pairs, parent_pairs = plan.pairs(), pplan.pairs()
     total = fine_pairs + cpairs + parent_pairs
-    log("two-level step %.2f ms: %d fine + %d coarse + %d parent-level pairs" % (
-        ms, fine_pairs, cpairs, parent_pairs))
+    log("two-level step%s %.2f ms: %d fine + %d coarse + %d parent-level pairs" % (
+        " (full truncation)" if full else "", ms, fine_pairs, cpairs, parent_pairs))
     tree.close()
     pplan.close()
     return {"mean_ms": round(ms, 3), "fine_pairs": fine_pairs, "coarse_pairs": cpairs,

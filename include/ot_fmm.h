@@ -187,6 +187,13 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
 int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp, double* L,
                        void* stream);
 
+/* The coarse substitutes under the full truncation (the reading of
+ * ot_fmm_multipole_batched_full, for a step that uses it):
+ *   L_a(i) += sum_{|b| <= 3} s_b M_b(J) G_{a+b}(X_i - X_J).
+ * Same tables, arguments, accumulation and errors as ot_fmm_coarse_fine. */
+int ot_fmm_coarse_fine_full(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp,
+                            double* L, void* stream);
+
 /* Batched multipole forward: M[20][S*512], com[3][S*512] -> L[20][T*512]. */
 int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
                              int sched, void* stream);

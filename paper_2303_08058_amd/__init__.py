@@ -73,8 +73,9 @@ _lib.ot_fmm_multipole_backward_full.argtypes = [_P, _P, _P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_backward_full.restype = _I
 _lib.ot_fmm_plan_set_coarse.argtypes = [_P, _I32, _P, _P, ctypes.POINTER(ctypes.c_int64)]
 _lib.ot_fmm_plan_set_coarse.restype = _I
-_lib.ot_fmm_coarse_fine.argtypes = [_P, _P, _P, _P, _P, _P]
-_lib.ot_fmm_coarse_fine.restype = _I
+for _f in (_lib.ot_fmm_coarse_fine, _lib.ot_fmm_coarse_fine_full):
+    _f.argtypes = [_P, _P, _P, _P, _P, _P]
+    _f.restype = _I
 _lib.ot_fmm_multipole_batched.argtypes = [_P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_batched.restype = _I
 _lib.ot_fmm_multipole_backward.argtypes = [_P, _P, _P, _P, _P, _P, _I, _P]
@@ -270,16 +271,17 @@ class Plan:
         self.Sp_coarse = int(Sp)
         return int(v.value)
 
-    def coarse_fine(self, com, Mp, comp, L, stream=None):
-        """Adds the coarse substitutes' contributions into L (20, T*512)."""
+    def coarse_fine(self, com, Mp, comp, L, stream=None, full=False):
+        """Adds the coarse substitutes' contributions into L (20, T*512);
+        full=True: under the full truncation (ot_fmm_coarse_fine_full)."""
         Sp = getattr(self, "Sp_coarse", 0)
         if Sp <= 0:
             raise ValueError("no coarse substitutes set")
         _, sx, sl = self._shapes()
-        _check(_lib.ot_fmm_coarse_fine(self.handle, _dptr(com, sx, "com"),
-                                       _dptr(Mp, (20, Sp * 512), "Mp"),
-                                       _dptr(comp, (3, Sp * 512), "comp"), _dptr(L, sl, "L"),
-                                       _stream(stream)), "ot_fmm_coarse_fine")
+        fn, name = ((_lib.ot_fmm_coarse_fine_full, "ot_fmm_coarse_fine_full") if full
+                    else (_lib.ot_fmm_coarse_fine, "ot_fmm_coarse_fine"))
+        _check(fn(self.handle, _dptr(com, sx, "com"), _dptr(Mp, (20, Sp * 512), "Mp"),
+                  _dptr(comp, (3, Sp * 512), "comp"), _dptr(L, sl, "L"), _stream(stream)), name)
         return L
 
     def _shapes(self):
@@ -375,6 +377,10 @@ def ot_fmm_plan_set_coarse(plan, Sp, coarse, octant):
 
 def ot_fmm_coarse_fine(plan, com, Mp, comp, L, stream=None):
     return plan.coarse_fine(com, Mp, comp, L, stream)
+
+
+def ot_fmm_coarse_fine_full(plan, com, Mp, comp, L, stream=None):
+    return plan.coarse_fine(com, Mp, comp, L, stream, full=True)
 
 
 class MultipoleBatched(torch.autograd.Function):

@@ -51,13 +51,18 @@ struct CoarseShape {
 // the order of the sums is fixed (slots, then J ascending): deterministic.
 // With 8 wavefronts (a whole target) the accumulators go through LDS at the
 // end so that L is read and written in cell order; smaller work-groups add
-// into their cells directly.
-template <int NW>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) k_coarse_fine(const CoarseParams p)
+// into their cells directly. FULL: the full truncation (every |b| <= 3 for
+// every |a| <= 3, derivatives of G to order 6), with the same staged values
+// and kept outputs as the total order; its derivatives need up to 256
+// registers, so it runs at half the waves per SIMD.
+template <int NW, bool FULL>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(FULL ? 2 : 4)))
+k_coarse_fine(const CoarseParams p)
 {
     using Sh = CoarseShape<NW>;
     constexpr int kNc = 3 + kNRed;                        // staged values per coarse cell
-    constexpr int kNa = ModeTraits<MODE_FWD_STORE>::nacc;  // kept L_a of the reduced form
+    constexpr int kNa = ModeTraits<MODE_FWD_STORE>::nacc;  // kept L_a of the reduced form (either truncation)
+    static_assert(ModeTraits<MODE_FULL_STORE>::nacc == kNa, "both truncations keep the same outputs");
     constexpr int kSlotVals = kNc * 64;
     __shared__ double s_src[Sh::batch * kSlotVals];
     __shared__ int s_slot[Sh::batch];
@@ -119,9 +124,16 @@ __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4)
             double f[kNc];
 #pragma unroll
             for (int k = 0; k < kNc; ++k) f[k] = src[k * 64];
-            double G[20];
-            green<3>(xi - f[0], yi - f[1], zi - f[2], G);
-            contract_red<0, TRUNC3>(acc, f + 3, G, std::make_integer_sequence<int, 20>{});
+            if constexpr (FULL) {
+                double D[7];
+                const double rr[3] = {xi - f[0], yi - f[1], zi - f[2]};
+                radial<6>(rr[0], rr[1], rr[2], D);
+                contract_full<0>(acc, f + 3, rr, D, std::make_integer_sequence<int, 20>{});
+            } else {
+                double G[20];
+                green<3>(xi - f[0], yi - f[1], zi - f[2], G);
+                contract_red<0, TRUNC3>(acc, f + 3, G, std::make_integer_sequence<int, 20>{});
+            }
         }
     }
     int oc = cell;

@@ -916,8 +916,8 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
     return OT_FMM_OK;
 }
 
-int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp, double* L,
-                       void* stream)
+static int coarse_fine_any(bool full, ot_fmm_plan plan, const double* com, const double* Mp, const double* comp,
+                           double* L, void* stream)
 {
     g_last_error.clear();
     int rc = check_plan(plan);
@@ -945,10 +945,25 @@ int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, co
     cp.out = L;
     cp.out_stride = NT;
     for (int k = 0; k < 3; ++k) cp.period[k] = plan->period[k];
-    hipLaunchKernelGGL(k_coarse_fine<kCoarseWaves>, dim3((unsigned)plan->n_coarse_items), dim3(kCoarseWaves * 64), 0,
-                       (hipStream_t)stream, cp);
+    const dim3 grid((unsigned)plan->n_coarse_items), block(kCoarseWaves * 64);
+    if (full)
+        hipLaunchKernelGGL((k_coarse_fine<kCoarseWaves, true>), grid, block, 0, (hipStream_t)stream, cp);
+    else
+        hipLaunchKernelGGL((k_coarse_fine<kCoarseWaves, false>), grid, block, 0, (hipStream_t)stream, cp);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
+}
+
+int ot_fmm_coarse_fine(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp, double* L,
+                       void* stream)
+{
+    return coarse_fine_any(false, plan, com, Mp, comp, L, stream);
+}
+
+int ot_fmm_coarse_fine_full(ot_fmm_plan plan, const double* com, const double* Mp, const double* comp, double* L,
+                            void* stream)
+{
+    return coarse_fine_any(true, plan, com, Mp, comp, L, stream);
 }
 
 int ot_fmm_plan_pairs(ot_fmm_plan plan, int64_t* pairs)

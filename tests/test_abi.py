@@ -122,8 +122,9 @@ def test_kernels_reject_null_and_misaligned_pointers(lib):
         assert fn(base + 4, base, base, None) == -1
     lib.ot_fmm_multipole_batched.argtypes = [P, P, P, P, ctypes.c_int, P]
     assert lib.ot_fmm_multipole_batched(None, None, None, None, 0, None) == -1
-    lib.ot_fmm_coarse_fine.argtypes = [P, P, P, P, P, P]
-    assert lib.ot_fmm_coarse_fine(None, None, None, None, None, None) == -1
+    for fn in (lib.ot_fmm_coarse_fine, lib.ot_fmm_coarse_fine_full):
+        fn.argtypes = [P, P, P, P, P, P]
+        assert fn(None, None, None, None, None, None) == -1
     lib.ot_fmm_plan_set_coarse.argtypes = [P, ctypes.c_int32, P, P, P]
     assert lib.ot_fmm_plan_set_coarse(None, 1, None, None, None) == -1
     lib.ot_fmm_last_error.restype = ctypes.c_char_p

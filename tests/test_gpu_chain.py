@@ -2,7 +2,8 @@
 upward pass of a fine store to its parent level, the fine interaction plus
 coarse substitutes for the fine level's missing neighbours, the interaction
 of the parent level, the downward pass of the parent expansions into the
-fine coefficients, and the evaluation of force and energy. The oracle runs
+fine coefficients, and the evaluation of force and energy; with either
+truncation of the interactions. The oracle runs
 the same chain of its own functions on the same seeded inputs; the test
 checks that every hand-over between the passes (layouts, centres, store
 and parent numbering) agrees.
@@ -38,8 +39,8 @@ def _host(t):
     return t.cpu().numpy()
 
 
-@pytest.mark.parametrize("periodic", [False, True])
-def test_two_level_step_matches_the_oracle_chain(periodic):
+@pytest.mark.parametrize("periodic,full", [(False, False), (True, False), (True, True)])
+def test_two_level_step_matches_the_oracle_chain(periodic, full):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_2303_08058_amd as ot
@@ -54,8 +55,9 @@ def test_two_level_step_matches_the_oracle_chain(periodic):
 
     # oracle chain
     Mp_r, Xp_r = oracle.m2m(children, M, X)
-    Lf_r = oracle.batched_forward(fine, M, X) + oracle.coarse_fine(fine, X, coarse, octant, Mp_r, Xp_r)
-    Lp_r = oracle.batched_forward(parent, Mp_r, Xp_r)
+    Lf_r = (oracle.batched_forward(fine, M, X, full=full) +
+            oracle.coarse_fine(fine, X, coarse, octant, Mp_r, Xp_r, full=full))
+    Lp_r = oracle.batched_forward(parent, Mp_r, Xp_r, full=full)
     Lf_r = oracle.l2l(children, Lp_r, Xp_r, X, Lf_r)
     F_r, W_r = oracle.evaluate(M, Lf_r)
 
@@ -68,11 +70,17 @@ def test_two_level_step_matches_the_oracle_chain(periodic):
     plan_f = ot.Plan.from_batch(fine)
     plan_f.set_coarse(Sp, coarse, octant)
     Lf = torch.empty((20, fine["T"] * SUB3), **f64)
-    plan_f.multipole_batched(dM, dX, Lf)
-    plan_f.coarse_fine(dX, Mp, Xp, Lf)
+    if full:
+        plan_f.multipole_batched_full(dM, dX, Lf)
+    else:
+        plan_f.multipole_batched(dM, dX, Lf)
+    plan_f.coarse_fine(dX, Mp, Xp, Lf, full=full)
     plan_p = ot.Plan.from_batch(parent)
     Lp = torch.empty((20, parent["T"] * SUB3), **f64)
-    plan_p.multipole_batched(Mp, Xp, Lp)
+    if full:
+        plan_p.multipole_batched_full(Mp, Xp, Lp)
+    else:
+        plan_p.multipole_batched(Mp, Xp, Lp)
     tree.l2l(Lp, Xp, dX, Lf)
     F = torch.empty((3, fine["S"] * SUB3), **f64)
     W = torch.empty((fine["S"] * SUB3,), **f64)

@@ -211,3 +211,46 @@ def test_no_substitutes_leaves_L_untouched(ot):
     plan.coarse_fine(dX, dMp, dXp, L)
     ref, A = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, want_abs=True)
     assert_parity(_host(L), ref, TOL, what="after replacing tables", A=A)
+
+
+# ---------------------------------------------------------------------------
+# the full truncation (every |b| <= 3 for every output |a| <= 3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("periodic", [True, False])
+def test_coarse_fine_full_small_all_targets(ot, periodic):
+    batch, M, X, coarse, octant, Mp, Xp = _case(4, 88 + periodic, 0.6, periodic)
+    plan = ot.Plan.from_batch(batch)
+    plan.set_coarse(Mp.shape[1] // SUB3, coarse, octant)
+    ref, A = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, want_abs=True, full=True)
+    L = _zeros(20, batch["T"] * SUB3)
+    dX, dMp, dXp = _dev(X), _dev(Mp), _dev(Xp)
+    plan.coarse_fine(dX, dMp, dXp, L, full=True)
+    got = _host(L)
+    assert_parity(got, ref, TOL, what="coarse full small", A=A)
+    # it is not the total order: the order-3 outputs differ by the added terms
+    ref_t = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp)
+    assert np.max(np.abs(ref[10:] - ref_t[10:])) > 1e-6 * np.max(np.abs(ref_t[10:]))
+    none = np.nonzero(~(coarse >= 0).any(1))[0]
+    assert np.all(got.reshape(20, -1, SUB3)[:, none] == 0.0)
+    plan.coarse_fine(dX, dMp, dXp, L, full=True)
+    assert np.array_equal(_host(L), 2.0 * got)
+
+
+def test_coarse_fine_full_config5_sampled(ot):
+    """32^3 sub-grids, periodic, 20% of targets missing 1..9 neighbours, all
+    substituted: the full-truncation launch over every target, sampled."""
+    batch, M, X = synthetic.config5()
+    coarse, octant = synthetic.coarse_tables(32, batch)
+    Mp, Xp = oracle.m2m(synthetic.octree_children(32), M, X)
+    plan = ot.Plan.from_batch(batch)
+    plan.set_coarse(Mp.shape[1] // SUB3, coarse, octant)
+    L = _zeros(20, batch["T"] * SUB3)
+    plan.coarse_fine(_dev(X), _dev(Mp), _dev(Xp), L, full=True)
+    got = _host(L)
+    assert np.all(np.isfinite(got))
+    with_sub = np.nonzero((coarse >= 0).any(1))[0]
+    rng = np.random.default_rng(89)
+    sel = np.sort(rng.choice(with_sub, 12, replace=False)).astype(np.int32)
+    ref, A = oracle.coarse_fine(batch, X, coarse, octant, Mp, Xp, tsel=sel, want_abs=True, full=True)
+    cols = got.reshape(20, -1, SUB3)[:, sel].reshape(20, -1)
+    assert_parity(cols, ref, TOL, what="config5 coarse full", A=A)
