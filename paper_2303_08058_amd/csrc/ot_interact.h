@@ -541,130 +541,81 @@ constexpr int lds_doubles()
     return plane > merge ? plane : merge;
 }
 
-// Staging of one halo z-plane: every global load of the calling thread is
-// issued first (stage_load), then the values are scaled and written into the
-// LDS plane (stage_store), back to back between two barriers. (Issuing the
-// next plane's loads before the barrier, to overlap the wait, was measured
-// slower: the held registers spill.)
-// Work unit ("chunk"): one component of one 8x8-cell block of the plane (one
-// of the 3x3 neighbour sub-grids crossing it); lane l takes cell
-// (l % 8, l / 8) of the block, so a wavefront reads 512 contiguous bytes.
-// Chunks are dealt to wavefronts round-robin, which keeps the component, the
-// block and all their address math wave-uniform (scalar registers); the
-// loop over chunks is branch-free (uniform selects) so that all loads of a
-// wavefront are in flight together. A missing neighbour is read at block 0
-// (valid memory) and replaced by zero moments and a far centre.
-template <int MODE>
-struct Chunk {
-    const double* src;   // first operand, already offset to the cell
-    const double* src2;  // second operand (the same address when unused)
-    double a1, a2;       // value = a1 * src + a2 * src2 (+ add)
-    double add, fill;
-    bool present;
-};
+// Staging of one source z-plane (the 24 x 24 cells of the 3 x 3 neighbour
+// blocks), one cell per thread: thread v takes cell v & 63 of block v >> 6
+// (the block is wavefront-uniform, so its relation is a scalar load), loads
+// the cell's centre and each of its moments once (every load of a wavefront
+// reads 512 contiguous bytes), forms the scaled trace-reduced sources with
+// compile-time factors, and writes the cell's record with 16-byte LDS
+// stores. A missing neighbour block is staged far away with zero sources.
+template <int MODE, int B>
+__device__ __forceinline__ double staged_source(const double* raw)
+{
+    constexpr bool rev = ModeTraits<MODE>::source_role;
+    constexpr int cP = kRedP[B], cS = kRedS[B];
+    constexpr double aP = rev ? parity_sign(cP) : parity_sign(cP) * inv_multi_factorial(cP);
+    if constexpr (cS < 0) {
+        return raw[cP] * aP;
+    } else {
+        constexpr double aS = rev ? parity_sign(cS) : parity_sign(cS) * inv_multi_factorial(cS);
+        return __builtin_fma(raw[cS], -aS, raw[cP] * aP);
+    }
+}
+template <int MODE, int... B>
+__device__ __forceinline__ void staged_sources(const double* raw, double* val, std::integer_sequence<int, B...>)
+{
+    ((val[3 + B] = staged_source<MODE, B>(raw)), ...);
+}
 
-// Component c of the staged plane: 0..2 centre of mass, 3.. source value b =
-// c - 3 -- the mass (monopole) or trace-reduced moment b, i.e. the
-// difference of two scaled moments.
-template <int MODE>
-__device__ __forceinline__ Chunk<MODE> chunk_of(const KParams& p, const int4* rel, int zs, int u,
-                                                int lane)
+template <int MODE, int NW>
+__device__ __forceinline__ void stage_plane(const KParams& p, const int4* rel, int zs, int tid, double* lds)
 {
     using T = ModeTraits<MODE>;
-    const int c = u / 9;
-    const int bxy = u - 9 * c;
-    const int by = bxy / 3, bx = bxy - 3 * by;
-    const bool isx = c < 3;
-    const int rb = isx ? 0 : c - 3;
-    const int cP = c_red_src[rb][0];
-    const int cS = c_red_src[rb][1];
-    const int cS2 = cS >= 0 ? cS : cP;
-    const int cx = isx ? c : 0;
-    const double* sc = T::source_role ? c_scale_rev : c_scale_fwd;
-    Chunk<MODE> ch;
-    long off, stride_c;
-    const double* base;
-    if constexpr (T::halo) {
-        off = (long)zs * kPlane + (by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7);
-        stride_c = kHalo3;
-        base = isx ? p.pos : p.mom;
-        ch.add = 0.0;
-        ch.fill = 0.0;
-        ch.present = true;
-    } else {
-        const int4 rr = rel[9 * (zs >> 3) + bxy];  // uniform address: scalar load
-        ch.present = rr.x >= 0;
-        const long blk = ch.present ? (isx ? rr.y : rr.x) : 0;
-        off = blk * kSub3 + 64 * (zs & 7) + lane;
-        stride_c = isx ? p.pos_stride : p.mom_stride;
-        base = isx ? p.pos : p.mom;
-        ch.add = isx ? (double)(int)(int8_t)((rr.z >> (8 * cx)) & 0xff) * p.period[cx] : 0.0;
-        ch.fill = isx ? kFar : 0.0;
-    }
-    ch.src = base + (long)(isx ? cx : cP) * stride_c + off;
-    ch.src2 = base + (long)(isx ? cx : cS2) * stride_c + off;
-    ch.a1 = isx ? 1.0 : sc[cP];
-    ch.a2 = (isx || cS < 0) ? 0.0 : -sc[cS2];
-    return ch;
-}
-
-template <int MODE>
-__device__ __forceinline__ int chunk_lds_index(int u, int lane)
-{
-    const int c = u / 9;
-    const int bxy = u - 9 * c;
-    const int by = bxy / 3, bx = bxy - 3 * by;
-    return ((by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7)) * Layout<MODE>::stride + c;
-}
-
-template <int MODE, int NW>
-struct PlaneLoad {
-    static constexpr int NCH = 9 * ModeTraits<MODE>::nc;  // chunks per plane
-    static constexpr int FULL = NCH / NW;                 // chunks every wavefront has
-    double raw[FULL + 1], raw2[FULL + 1];
-};
-
-// Phase 1: issue every global load of the wavefront's chunks of plane zs.
-template <int MODE, int NW>
-__device__ __forceinline__ void stage_load(PlaneLoad<MODE, NW>& pl, const KParams& p,
-                                           const int4* rel, int zs, int wave, int lane)
-{
-    constexpr int NCH = PlaneLoad<MODE, NW>::NCH;
-    constexpr int FULL = PlaneLoad<MODE, NW>::FULL;
+    using Lay = Layout<MODE>;
+    constexpr int nm = (T::nq == 1) ? 1 : 20;  // moments read per cell
+    for (int v = tid; v < 9 * 64; v += NW * 64) {
+        const int bxy = __builtin_amdgcn_readfirstlane(v >> 6);
+        const int lane = v & 63;
+        const int by = bxy / 3, bx = bxy - 3 * by;
+        const double* pm;
+        const double* px;
+        long sm, sx;
+        double sh[3] = {0.0, 0.0, 0.0};
+        bool present = true;
+        if constexpr (T::halo) {
+            const long off = (long)zs * kPlane + (by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7);
+            pm = p.mom + off;
+            px = p.pos + off;
+            sm = sx = kHalo3;
+        } else {
+            const int4 rr = rel[9 * (zs >> 3) + bxy];  // uniform address: scalar load
+            present = rr.x >= 0;
+            const long o = 64 * (zs & 7) + lane;
+            pm = p.mom + (present ? (long)rr.x * kSub3 : 0) + o;
+            px = p.pos + (present ? (long)rr.y * kSub3 : 0) + o;
+            sm = p.mom_stride;
+            sx = p.pos_stride;
 #pragma unroll
-    for (int k = 0; k < FULL; ++k) {
-        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, wave + k * NW, lane);
-        pl.raw[k] = *ch.src;
-        pl.raw2[k] = *ch.src2;
-    }
-    pl.raw[FULL] = pl.raw2[FULL] = 0.0;
-    if (wave + FULL * NW < NCH) {
-        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, wave + FULL * NW, lane);
-        pl.raw[FULL] = *ch.src;
-        pl.raw2[FULL] = *ch.src2;
-    }
-}
-
-// Phase 2: scale / combine / shift the loaded values and write the LDS plane.
-template <int MODE, int NW>
-__device__ __forceinline__ void stage_store(const PlaneLoad<MODE, NW>& pl, const KParams& p,
-                                            const int4* rel, int zs, int wave, int lane,
-                                            double* lds)
-{
-    constexpr int NCH = PlaneLoad<MODE, NW>::NCH;
-    constexpr int FULL = PlaneLoad<MODE, NW>::FULL;
+            for (int k = 0; k < 3; ++k) sh[k] = (double)(int)(int8_t)((rr.z >> (8 * k)) & 0xff) * p.period[k];
+        }
+        double val[2 * Lay::nvec];
 #pragma unroll
-    for (int k = 0; k < FULL; ++k) {
-        const int u = wave + k * NW;
-        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
-        const double v = __builtin_fma(pl.raw2[k], ch.a2, pl.raw[k] * ch.a1) + ch.add;
-        lds[chunk_lds_index<MODE>(u, lane)] = ch.present ? v : ch.fill;
-    }
-    if (wave + FULL * NW < NCH) {
-        const int u = wave + FULL * NW;
-        const Chunk<MODE> ch = chunk_of<MODE>(p, rel, zs, u, lane);
-        const double v = __builtin_fma(pl.raw2[FULL], ch.a2, pl.raw[FULL] * ch.a1) + ch.add;
-        lds[chunk_lds_index<MODE>(u, lane)] = ch.present ? v : ch.fill;
+        for (int c = 0; c < 2 * Lay::nvec; ++c) val[c] = 0.0;
+        if (present) {
+            double raw[nm];
+#pragma unroll
+            for (int c = 0; c < nm; ++c) raw[c] = pm[c * sm];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) val[k] = px[k * sx] + sh[k];
+            staged_sources<MODE>(raw, val, std::make_integer_sequence<int, T::nq>{});
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) val[k] = kFar;
+        }
+        double2* dst = reinterpret_cast<double2*>(
+            lds + ((by * 8 + (lane >> 3)) * kHalo + bx * 8 + (lane & 7)) * Lay::stride);
+#pragma unroll
+        for (int j = 0; j < Lay::nvec; ++j) dst[j] = make_double2(val[2 * j], val[2 * j + 1]);
     }
 }
 
@@ -755,15 +706,9 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
                        : (NP == 2 ? (pass == 0 ? 0 : 8 + 4 - kReach) : 0);
     const int zs_end = SPLIT ? (8 + zt + kReach + 1 < kHalo ? 8 + zt + kReach + 1 : kHalo)
                      : (NP == 2 ? (pass == 0 ? 8 + 3 + kReach + 1 : kHalo) : kHalo);
-    // the next plane's loads are issued as soon as a wavefront is done with
-    // the current one, so they overlap the barrier wait
     for (int zs = zs_begin; zs < zs_end; ++zs) {
         __syncthreads();
-        {
-            PlaneLoad<MODE, NW> pl;
-            stage_load<MODE, NW>(pl, p, s_rel, zs, wave, lane);
-            stage_store<MODE, NW>(pl, p, s_rel, zs, wave, lane, lds);
-        }
+        stage_plane<MODE, NW>(p, s_rel, zs, tid, lds);
         __syncthreads();
         const int dz = zs - (8 + zt);
         if (dz >= -kReach && dz <= kReach) {
