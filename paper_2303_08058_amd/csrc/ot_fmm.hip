@@ -160,9 +160,18 @@ struct ot_fmm_plan_s {
     int* d_rev_order = nullptr; // [S]
     int* d_fwd_local = nullptr; // [T] XCD-aware (OT_FMM_SCHED_LOCAL)
     int* d_rev_local = nullptr; // [S]
+    // the same XCD-aware pieces stored one after the other (persistent
+    // launches in the local order: a counter per piece); npieces = 0 when the
+    // device has more XCDs than kMaxPieces
+    int* d_fwd_piece = nullptr; // [T]
+    int* d_rev_piece = nullptr; // [S]
+    int npieces = 0;
+    int fwd_piece_off[kMaxPieces + 1] = {0};
+    int rev_piece_off[kMaxPieces + 1] = {0};
     int tuned_fwd = 0, tuned_bwd = 0;
-    // persistent launches: one work counter per launch in flight (rotating)
-    int* d_counters = nullptr;  // [kCounterSlots]
+    // persistent launches: one set of kMaxPieces work counters per launch in
+    // flight (rotating)
+    int* d_counters = nullptr;  // [kCounterSlots][kMaxPieces]
     std::atomic<unsigned> next_counter{0};
     int n_cu = 0;
     hipGraph_t graph = nullptr;
@@ -236,8 +245,8 @@ int launch_timed(ot_fmm_plan plan, int which, KParams kp, int nblocks, bool pers
     int rc = timing_begin(plan, which, stream, &ev);
     if (rc) return rc;
     if (persistent && nblocks > 0) {
-        int* c = plan->d_counters + plan->next_counter.fetch_add(1) % kCounterSlots;
-        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, stream, c);
+        int* c = plan->d_counters + (size_t)(plan->next_counter.fetch_add(1) % kCounterSlots) * kMaxPieces;
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(kMaxPieces), 0, stream, c);
         kp.counter = c;
         kp.n_items = nblocks;
         const long resident = (long)plan->n_cu * resident_per_cu<MODE, NW, NP>();
@@ -247,6 +256,22 @@ int launch_timed(ot_fmm_plan plan, int which, KParams kp, int nblocks, bool pers
                     : launch<MODE, NW, false, NP, false>(kp, nblocks, stream);
     if (rc) return rc;
     return timing_end(ev, stream);
+}
+
+// The work order of a launch: XCD-aware (OT_FMM_SCHED_LOCAL) or longest work
+// first (already in kp.order); a persistent launch in the XCD-aware order
+// takes the pieces with a counter each.
+void apply_order(KParams& kp, const ot_fmm_plan_s* plan, int sched, bool rev)
+{
+    if (!(sched & OT_FMM_SCHED_LOCAL)) return;
+    if ((sched & OT_FMM_SCHED_PERSISTENT) && plan->npieces > 0) {
+        kp.order = rev ? plan->d_rev_piece : plan->d_fwd_piece;
+        kp.npieces = plan->npieces;
+        const int* off = rev ? plan->rev_piece_off : plan->fwd_piece_off;
+        for (int k = 0; k <= plan->npieces; ++k) kp.piece_off[k] = off[k];
+    } else {
+        kp.order = rev ? plan->d_rev_local : plan->d_fwd_local;
+    }
 }
 
 int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, int sched,
@@ -266,7 +291,7 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
     sched = pick_fwd(sched, plan->tuned_fwd);
     const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
-    if (sched & OT_FMM_SCHED_LOCAL) kp.order = plan->d_fwd_local;
+    apply_order(kp, plan, sched, false);
     const int shape = sched & kShapeMask;
     if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FWD_STORE, 8>(plan, 0, kp, plan->T, pers, stream);
     if (shape == OT_FMM_SCHED_W16)
@@ -295,7 +320,7 @@ int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
     if (sched == OT_FMM_SCHED_AUTO) sched = OT_FMM_SCHED_W8;
     const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
-    if (sched & OT_FMM_SCHED_LOCAL) kp.order = plan->d_fwd_local;
+    apply_order(kp, plan, sched, false);
     const int shape = sched & kShapeMask;
     if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FULL_STORE, 8>(plan, -1, kp, plan->T, pers, stream);
     if (shape == OT_FMM_SCHED_W16)
@@ -346,7 +371,7 @@ int bwd_any(ot_fmm_plan plan, const double* M, const double* com, const double* 
     // the source-role pass has 8 wavefronts (its 40 accumulators do not fit
     // the register budget of 16): one pass, or two with split rows
     const bool spers = (ssched & OT_FMM_SCHED_PERSISTENT) != 0;
-    if (ssched & OT_FMM_SCHED_LOCAL) b2.order = plan->d_rev_local;
+    apply_order(b2, plan, ssched, true);
     int rc = (ssched & kShapeMask) == OT_FMM_SCHED_W8P2
                  ? launch_timed<kB2, 8, 2>(plan, w2, b2, plan->S, spers, stream)
                  : launch_timed<kB2, 8>(plan, w2, b2, plan->S, spers, stream);
@@ -367,7 +392,7 @@ int bwd_any(ot_fmm_plan plan, const double* M, const double* com, const double* 
     b1.out_blk = plan->d_tgt;
     for (int k = 0; k < 3; ++k) b1.period[k] = plan->period[k];
     const bool tpers = (tsched & OT_FMM_SCHED_PERSISTENT) != 0;
-    if (tsched & OT_FMM_SCHED_LOCAL) b1.order = plan->d_fwd_local;
+    apply_order(b1, plan, tsched, false);
     const int tshape = tsched & kShapeMask;
     if constexpr (!FULL)
         if (tshape == OT_FMM_SCHED_W16) return launch_timed<kB1, 16>(plan, w1, b1, plan->T, tpers, stream);
@@ -409,6 +434,8 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_rev_order);
     (void)hipFree(p->d_fwd_local);
     (void)hipFree(p->d_rev_local);
+    (void)hipFree(p->d_fwd_piece);
+    (void)hipFree(p->d_rev_piece);
     (void)hipFree(p->d_counters);
     (void)hipFree(p->d_cf_items);
     (void)hipFree(p->d_cf_entries);
@@ -458,7 +485,8 @@ uint64_t spread_bits(uint64_t v)  // 21 bits -> every third bit
 // its concurrently resident work-groups stage overlap and are found in its L2.
 // adj[v] lists (neighbour entry, slot of the neighbour seen from v).
 std::vector<int> locality_order(const std::vector<std::vector<std::pair<int, int>>>& adj,
-                                const std::vector<int64_t>& work, int nxcd)
+                                const std::vector<int64_t>& work, int nxcd, std::vector<int>* pieces = nullptr,
+                                std::vector<int>* piece_off = nullptr)
 {
     const int n = (int)adj.size();
     std::vector<int> comp(n, -1);
@@ -509,6 +537,14 @@ std::vector<int> locality_order(const std::vector<std::vector<std::pair<int, int
         piece[x].push_back(v);
         run += work[v];
     }
+    if (pieces && piece_off) {
+        pieces->clear();
+        piece_off->assign(1, 0);
+        for (int x = 0; x < nxcd; ++x) {
+            pieces->insert(pieces->end(), piece[x].begin(), piece[x].end());
+            piece_off->push_back((int)pieces->size());
+        }
+    }
     std::vector<int> order;
     order.reserve(n);
     for (size_t i = 0; order.size() < (size_t)n; ++i)
@@ -531,6 +567,7 @@ struct HostTables {
     std::vector<int64_t> fwd_work;
     std::vector<int> tg, fo, ro;
     std::vector<int> fo_local, ro_local;  // XCD-aware orders (filled by make_local_orders)
+    std::vector<int> fo_piece, ro_piece, fo_off, ro_off;  // the same, piece after piece
     std::vector<int64_t> rev_work;
     int64_t pairs = 0;
 };
@@ -550,8 +587,8 @@ void make_local_orders(int32_t S, int32_t T, const int32_t* nbr, HostTables* h, 
             // store block b sees the target's own block at the opposite slot
             radj[b].emplace_back(h->tg[t], 26 - q);
         }
-    h->fo_local = locality_order(adj, h->fwd_work, nxcd);
-    h->ro_local = locality_order(radj, h->rev_work, nxcd);
+    h->fo_local = locality_order(adj, h->fwd_work, nxcd, &h->fo_piece, &h->fo_off);
+    h->ro_local = locality_order(radj, h->rev_work, nxcd, &h->ro_piece, &h->ro_off);
 }
 
 int build_host_tables(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr, const int8_t* shift,
@@ -717,11 +754,17 @@ int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
     if (hipDeviceGetAttribute(&nxcd, hipDeviceAttributeNumberOfXccs, p->device) != hipSuccess || nxcd < 1)
         nxcd = 1;
     make_local_orders(S, T, nbr, &ht, nxcd);
-    const std::vector<int> zeros(kCounterSlots, 0);
+    p->npieces = nxcd <= kMaxPieces ? nxcd : 0;
+    for (int k = 0; k <= p->npieces; ++k) {
+        p->fwd_piece_off[k] = ht.fo_off[k];
+        p->rev_piece_off[k] = ht.ro_off[k];
+    }
+    const std::vector<int> zeros((size_t)kCounterSlots * kMaxPieces, 0);
     if ((rc = upload(&p->d_fwd_rel, fwd)) || (rc = upload(&p->d_rev_rel, rev)) ||
         (rc = upload(&p->d_tgt, tg)) || (rc = upload(&p->d_fwd_order, fo)) ||
         (rc = upload(&p->d_rev_order, ro)) || (rc = upload(&p->d_counters, zeros)) ||
-        (rc = upload(&p->d_fwd_local, ht.fo_local)) || (rc = upload(&p->d_rev_local, ht.ro_local))) {
+        (rc = upload(&p->d_fwd_local, ht.fo_local)) || (rc = upload(&p->d_rev_local, ht.ro_local)) ||
+        (rc = upload(&p->d_fwd_piece, ht.fo_piece)) || (rc = upload(&p->d_rev_piece, ht.ro_piece))) {
         free_plan_memory(p);
         delete p;
         return rc;

@@ -481,6 +481,8 @@ enum Mode : int {
     MODE_B1F_STORE = 7    // adjoint of the full truncation, target role -> gX (accumulate)
 };
 
+constexpr int kMaxPieces = 16;  // work-list pieces (one per XCD) of a persistent launch
+
 struct KParams {
     const double* mom;   // source moments / masses / weights, [ncomp][mom_stride]
     const double* pos;   // centres of mass, [3][pos_stride] (halo or store)
@@ -496,8 +498,13 @@ struct KParams {
     long out_stride;
     const int* out_blk;    // owner -> output block (NULL: identity)
     double period[3];
-    int* counter;          // persistent launch: work counter, zeroed before the launch
+    int* counter;          // persistent launch: work counter(s), zeroed before the launch
     int n_items;           // persistent launch: number of work-list entries
+    // persistent launch in pieces (npieces > 0): the work list is cut into
+    // npieces consecutive pieces, [piece_off[k], piece_off[k + 1]), one per
+    // XCD, each with its own counter counter[k]
+    int npieces;
+    int piece_off[kMaxPieces + 1];
 };
 
 template <int MODE>
@@ -651,11 +658,32 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     static_assert(!PERSIST || !T::halo, "persistent launches: batched forms");
     constexpr bool persistent = PERSIST;
     int item = (int)blockIdx.x;
+    // in pieces: the work-group starts on the piece of its XCD (work-group b
+    // runs on XCD b mod npieces) and moves on to the next piece when that is
+    // exhausted, until every piece is (s_step: pieces left behind)
+    __shared__ int s_step;
+    if (persistent && tid == 0) s_step = 0;
 #pragma unroll 1
     for (;;) {
     if (persistent) {
         __syncthreads();  // the previous entry is finished by every wavefront
-        if (tid == 0) s_item = atomicAdd(p.counter, 1);
+        if (tid == 0) {
+            int it = p.n_items;
+            if (p.npieces > 0) {
+                for (int step = s_step; step < p.npieces; ++step) {
+                    const int k = ((int)blockIdx.x + step) % p.npieces;
+                    const int i = atomicAdd(p.counter + k, 1);
+                    if (i < p.piece_off[k + 1] - p.piece_off[k]) {
+                        it = p.piece_off[k] + i;
+                        s_step = step;
+                        break;
+                    }
+                }
+            } else {
+                it = atomicAdd(p.counter, 1);
+            }
+            s_item = it;
+        }
         __syncthreads();
         item = __builtin_amdgcn_readfirstlane(s_item);
         if (item >= p.n_items) break;
@@ -875,6 +903,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
     }  // work-list entries
 }
 
-__global__ void k_zero_counter(int* c) { *c = 0; }
+// zeroes the kMaxPieces counters of a persistent launch (one per lane)
+__global__ void k_zero_counter(int* c) { c[threadIdx.x] = 0; }
 
 }  // namespace

@@ -46,7 +46,7 @@ def _empty(*shape):
 
 
 # 1 W8, 2 W16, 3 W8P2; 0x10 persistent; 0x20 XCD-aware work order
-@pytest.mark.parametrize("sched", [0, 1, 2, 3, 0x11, 0x21])
+@pytest.mark.parametrize("sched", [0, 1, 2, 3, 0x11, 0x21, 0x31, 0x33])
 def test_full_small_periodic_with_missing(ot, sched):
     batch, M, X = synthetic.batched_config(2, 23, missing_frac=0.5)
     ref, A = oracle.batched_forward(batch, M, X, want_abs=True, full=True)
@@ -131,7 +131,7 @@ def small_adjoint_case():
     return batch, M, X, w, gM_ref, gX_ref
 
 
-@pytest.mark.parametrize("sched", [0, 0x0101, 0x0303, 0x2111, 0x1121])
+@pytest.mark.parametrize("sched", [0, 0x0101, 0x0303, 0x2111, 0x1121, 0x3331])
 def test_full_adjoint_small_periodic_with_missing(ot, small_adjoint_case, sched):
     batch, M, X, w, gM_ref, gX_ref = small_adjoint_case
     plan = ot.Plan.from_batch(batch)
@@ -190,7 +190,7 @@ def test_full_adjoint_rejects_16_wavefronts(ot):
     assert e.value.code == ot.OT_FMM_EINVAL
 
 
-@pytest.mark.parametrize("fsched,bsched", [(1, 0x0101), (0x11, 0x1111)])
+@pytest.mark.parametrize("fsched,bsched", [(1, 0x0101), (0x11, 0x1111), (0x33, 0x3331)])
 def test_full_caller_captured_graph_replays(ot, fsched, bsched):
     """The full forward and its adjoint captured into a caller's graph
     (torch.cuda.CUDAGraph) replay bit for bit like the eager launches,

@@ -59,7 +59,7 @@ def test_multipole_single_block(ot):
 
 # 1 W8, 2 W16, 3 W8P2; 0x10 = persistent launch
 # 0x20 = XCD-aware work order
-@pytest.mark.parametrize("sched", [1, 2, 3, 0x11, 0x12, 0x13, 0x22, 0x31])
+@pytest.mark.parametrize("sched", [1, 2, 3, 0x11, 0x12, 0x13, 0x22, 0x31, 0x32, 0x33])
 def test_batched_small_periodic_with_missing(ot, sched):
     batch, M, X = synthetic.batched_config(2, 21, missing_frac=0.5)
     ref = oracle.batched_forward(batch, M, X)
@@ -130,7 +130,7 @@ def _small_adjoint_case():
 
 # (target-role schedule, source-role schedule)
 @pytest.mark.parametrize("sched", [(1, 1), (2, 1), (3, 3), (2, 3), (0x12, 0x11), (0x11, 0x13), (0x22, 0x21),
-                                   (0x32, 0x31)])
+                                   (0x32, 0x31), (0x32, 0x33)])
 def test_backward_small_open(ot, sched):
     batch, M, X = _small_adjoint_case()
     w = synthetic.weights(batch["T"], 42)
@@ -197,15 +197,15 @@ def test_autograd_function_matches_oracle(ot):
     assert L.dtype == torch.float64
 
 
-@pytest.mark.parametrize("persistent", [False, True])
+@pytest.mark.parametrize("persistent", [0, 0x10, 0x30])
 def test_step_graph_replays_match_eager(ot, persistent):
     """The captured forward+adjoint graph, replayed several times with eager
     work and synchronisations in between, reproduces the eager results
     bitwise on every replay (persistent launches: the work counters are
     zeroed by a kernel node of the graph on every replay)."""
     import torch
-    P = 0x10 if persistent else 0
-    fs, bs = 2 | P, ot.sched_bwd(2 | P, 1 | P)
+    P = persistent  # 0x10 persistent, 0x30 persistent in the XCD-aware pieces
+    fs, bs = 2 | P, ot.sched_bwd(2 | P, (3 if P == 0x30 else 1) | P)
     batch, M, X = synthetic.batched_config(3, 71, missing_frac=0.3)
     plan = ot.Plan.from_batch(batch)
     Md, Xd = _dev(M), _dev(X)
@@ -213,7 +213,7 @@ def test_step_graph_replays_match_eager(ot, persistent):
     NS, NT = batch["S"] * 512, batch["T"] * 512
     L0, gM0, gX0 = _empty(20, NT), _empty(20, NS), _empty(3, NS)
     plan.multipole_batched(Md, Xd, L0, sched=fs & 0xF)
-    plan.multipole_backward(Md, Xd, wd, gM0, gX0, sched=ot.sched_bwd(2, 1))
+    plan.multipole_backward(Md, Xd, wd, gM0, gX0, sched=ot.sched_bwd(2, bs >> 8 & 0xF))
     L, gM, gX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
     plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
     for rep in range(3):
@@ -270,7 +270,7 @@ def _cols(a, sel):
     return a.reshape(a.shape[0], -1, 512)[:, sel].reshape(a.shape[0], -1)
 
 
-@pytest.mark.parametrize("sched", [1, 2, 3, 0x12, 0x22])
+@pytest.mark.parametrize("sched", [1, 2, 3, 0x12, 0x22, 0x32])
 def test_config3_forward_sampled(ot, sched):
     """16^3 sub-grids, periodic, 15% missing 1-9 neighbours: every output of
     the launch is produced, a seeded sample of targets (half of them with
@@ -441,7 +441,7 @@ def test_overlapping_outputs_rejected(ot):
     assert torch.equal(Mb, Md)  # untouched
 
 
-@pytest.mark.parametrize("sched", [0x22, 0x12])
+@pytest.mark.parametrize("sched", [0x22, 0x12, 0x32])
 def test_concurrent_launches_of_one_plan_on_two_streams(ot, sched):
     """Two forward launches of the same plan in flight at once on two streams
     (persistent launches take separate counter slots) give the eager result."""
@@ -463,7 +463,7 @@ def test_concurrent_launches_of_one_plan_on_two_streams(ot, sched):
         assert torch.equal(L, ref)
 
 
-@pytest.mark.parametrize("sched", [0x22, 0x12])
+@pytest.mark.parametrize("sched", [0x22, 0x12, 0x32])
 def test_caller_captured_graph_replays(ot, sched):
     """The batched forward captured into a caller's graph (torch.cuda.CUDAGraph)
     replays correctly several times, with eager work in between (the
