@@ -228,8 +228,11 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
 
 /* Times every schedule of the forward (and backward, if gL/gM/gcom are not
  * NULL) on the given buffers and stores the fastest in the plan; returns the
- * choices. Synchronizes `stream`; do not call it while capturing. The buffers
- * are overwritten with valid results of the last timed schedule. */
+ * choices. Every shape is timed with each combination of the persistent and
+ * XCD-aware flags, the forward and the two adjoint passes each on its own.
+ * Synchronizes `stream`; do not call it while capturing. The buffers are
+ * overwritten with valid results (L of the last forward timed, gM and gcom
+ * of one backward with the chosen schedules). */
 int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double* L,
                     const double* gL, double* gM, double* gcom, void* stream,
                     int* fwd_sched, int* bwd_sched);

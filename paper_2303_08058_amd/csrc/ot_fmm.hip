@@ -336,8 +336,10 @@ int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
 // by the plan's events).
 template <bool FULL>
 int bwd_any(ot_fmm_plan plan, const double* M, const double* com, const double* gL, double* gM,
-            double* gcom, int sched, hipStream_t stream)
+            double* gcom, int sched, hipStream_t stream, int passes = 3)
 {
+    // passes: bit 0 the source-role pass, bit 1 the target-role pass (the
+    // autotuner times them one at a time; callers always run both)
     constexpr int kB2 = FULL ? MODE_B2F_STORE : MODE_B2_STORE;
     constexpr int kB1 = FULL ? MODE_B1F_STORE : MODE_B1_STORE;
     const int w2 = FULL ? -1 : 1, w1 = FULL ? -1 : 2;
@@ -372,10 +374,13 @@ int bwd_any(ot_fmm_plan plan, const double* M, const double* com, const double* 
     // the register budget of 16): one pass, or two with split rows
     const bool spers = (ssched & OT_FMM_SCHED_PERSISTENT) != 0;
     apply_order(b2, plan, ssched, true);
-    int rc = (ssched & kShapeMask) == OT_FMM_SCHED_W8P2
-                 ? launch_timed<kB2, 8, 2>(plan, w2, b2, plan->S, spers, stream)
-                 : launch_timed<kB2, 8>(plan, w2, b2, plan->S, spers, stream);
-    if (rc) return rc;
+    if (passes & 1) {
+        const int rc = (ssched & kShapeMask) == OT_FMM_SCHED_W8P2
+                           ? launch_timed<kB2, 8, 2>(plan, w2, b2, plan->S, spers, stream)
+                           : launch_timed<kB2, 8>(plan, w2, b2, plan->S, spers, stream);
+        if (rc) return rc;
+    }
+    if (!(passes & 2)) return OT_FMM_OK;
     // target role: owners are targets, sources their neighbours' cells
     KParams b1{};
     b1.mom = M;
@@ -1147,7 +1152,11 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
         OT_HIP(hipEventElapsedTime(ms, e0, e1));
         return OT_FMM_OK;
     };
-    // forward: every shape, then the winner as a persistent launch
+    // every shape with every combination of the persistent launch and the
+    // XCD-aware order, for each pass on its own: the forward, then the
+    // source-role pass, then the target-role pass
+    const int kFlags[4] = {0, OT_FMM_SCHED_PERSISTENT, OT_FMM_SCHED_LOCAL,
+                           OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL};
     int best_f = OT_FMM_SCHED_W16;
     float best_ms = 3.0e38f;
     auto try_fwd = [&](int cand) -> int {
@@ -1159,32 +1168,35 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
         }
         return r;
     };
-    for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2})
-        if ((rc = try_fwd(cand))) break;
-    if (!rc) rc = try_fwd(best_f | OT_FMM_SCHED_PERSISTENT);
-    if (!rc) rc = try_fwd(best_f | OT_FMM_SCHED_LOCAL);
+    for (int shape : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2})
+        for (int f : kFlags)
+            if (!rc) rc = try_fwd(shape | f);
     int best_b = OT_FMM_SCHED_W16 | (kDefaultSourceSched << 8);
     if (!rc && with_bwd) {
-        // source role first (target role W16), then the target role with it
-        best_ms = 3.0e38f;
-        auto try_bwd = [&](int sc) -> int {
+        // source role (bits 8..15), timed alone; then the target role
+        int best_s = kDefaultSourceSched, best_t = OT_FMM_SCHED_W16;
+        auto try_pass = [&](int passes, int sc, int* best) -> int {
             float ms = 0.0f;
-            int r = time_it([&] { return bwd_batched(plan, M, com, gL, gM, gcom, sc, s); }, &ms);
+            const int full = passes == 1 ? (OT_FMM_SCHED_W16 | (sc << 8)) : (sc | (best_s << 8));
+            int r = time_it([&] { return bwd_any<false>(plan, M, com, gL, gM, gcom, full, s, passes); }, &ms);
             if (!r && ms < best_ms) {
                 best_ms = ms;
-                best_b = sc;
+                *best = sc;
             }
             return r;
         };
-        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
-            if ((rc = try_bwd(OT_FMM_SCHED_W16 | (cand << 8)))) break;
-        if (!rc) rc = try_bwd(best_b | (OT_FMM_SCHED_PERSISTENT << 8));
-        if (!rc) rc = try_bwd(best_b | (OT_FMM_SCHED_LOCAL << 8));
-        const int src = best_b >> 8;
-        for (int cand : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
-            if (!rc) rc = try_bwd(cand | (src << 8));
-        if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_PERSISTENT);
-        if (!rc) rc = try_bwd(best_b | OT_FMM_SCHED_LOCAL);
+        best_ms = 3.0e38f;
+        for (int shape : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
+            for (int f : kFlags)
+                if (!rc) rc = try_pass(1, shape | f, &best_s);
+        best_ms = 3.0e38f;
+        for (int shape : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W16, OT_FMM_SCHED_W8P2})
+            for (int f : kFlags)
+                if (!rc) rc = try_pass(2, shape | f, &best_t);
+        best_b = best_t | (best_s << 8);
+        // the target-role trials accumulated into gcom: leave valid results
+        if (!rc) rc = bwd_batched(plan, M, com, gL, gM, gcom, best_b, s);
+        if (!rc) OT_HIP(hipStreamSynchronize(s));
     }
     if (rc) return rc;
     plan->tuned_fwd = best_f;

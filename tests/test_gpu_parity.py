@@ -241,6 +241,26 @@ def test_autotune_choices_are_valid_and_exact(ot):
     assert_parity(got, ref, TOL, what="autotuned")
 
 
+def test_autotune_with_the_adjoint_leaves_valid_results(ot):
+    """Autotuning both passes times the source- and target-role passes apart;
+    afterwards gM and gcom hold the adjoint of the chosen schedules, and the
+    tuned AUTO backward gives the same results bitwise."""
+    batch, M, X = synthetic.batched_config(2, 82, missing_frac=0.5)
+    w = synthetic.weights(batch["T"], 83)
+    plan = ot.Plan.from_batch(batch)
+    NS, NT = batch["S"] * 512, batch["T"] * 512
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    L, gM, gX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
+    f, b = plan.autotune(Md, Xd, L, wd, gM, gX)
+    assert (b & 0xF) in (1, 2, 3) and ((b >> 8) & 0xF) in (1, 3) and not (b & ~0x3F3F)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w)
+    assert_parity(_host(gM), gM_ref, TOL, what="autotune gM")
+    assert_parity(_host(gX), gX_ref, TOL, what="autotune gX")
+    gM2, gX2 = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward(Md, Xd, wd, gM2, gX2)  # AUTO -> tuned
+    assert np.array_equal(_host(gM2), _host(gM)) and np.array_equal(_host(gX2), _host(gX))
+
+
 def test_invalid_schedule_rejected(ot):
     batch, M, X = synthetic.batched_config(2, 91)
     plan = ot.Plan.from_batch(batch)
