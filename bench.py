@@ -401,7 +401,8 @@ def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None, wd=Non
     """Times the full-truncation forward on the benchmark plan: the given
     schedule, or the fastest of three over one launch each, then `steps`
     timed launches (HIP events on the launch stream); with weights and
-    gradient arrays also its adjoint (both passes, 8 wavefronts each)."""
+    gradient arrays also its adjoint (both passes with the library's default
+    schedule)."""
     stream = torch.cuda.current_stream()
 
     def timed(sched, n):
@@ -415,7 +416,8 @@ def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None, wd=Non
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n
 
-    cands = {ot.SCHED_W8: "W8", ot.SCHED_W8 | ot.SCHED_LOCAL: "W8+xcd-local", ot.SCHED_W8P2: "W8P2"}
+    default = ot.SCHED_W8P2 | ot.SCHED_PERSISTENT | ot.SCHED_LOCAL  # the library's AUTO for this truncation
+    cands = {sc: sched_name(sc) for sc in (default, ot.SCHED_W8, ot.SCHED_W8P2)}
     if sched is not None:
         cands = {sched: sched_name(sched)}
     plan.multipole_batched_full(Md, Xd, L, sched=next(iter(cands)))  # warm-up

@@ -203,14 +203,15 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
  *   L_a(i) = sum_{j in S(i)} sum_{|b| <= 3} s_b M_b(j) G_{a+b}(X_i - X_j),
  * the alternative to the total-order truncation |a| + |b| <= 3 of
  * ot_fmm_multipole_batched (Sec. 2.1 names the FMM without its truncation;
- * this is the other reading). Same plan, layouts, schedules (AUTO = W8) and
+ * this is the other reading). Same plan, layouts, schedules (AUTO = W8P2 |
+ * PERSISTENT | LOCAL, not autotuned) and
  * error rules as ot_fmm_multipole_batched; L is overwritten. */
 int ot_fmm_multipole_batched_full(ot_fmm_plan plan, const double* M, const double* com, double* L,
                                   int sched, void* stream);
 
 /* Adjoint of ot_fmm_multipole_batched_full (derivatives of G to order 7):
  * the same arrays, overwrite rules and errors as ot_fmm_multipole_backward;
- * schedules as there, AUTO = 8 wavefronts for both passes, a target-role
+ * schedules as there, AUTO = W8P2 | PERSISTENT | LOCAL for both passes, a target-role
  * shape of 16 wavefronts is EINVAL. */
 int ot_fmm_multipole_backward_full(ot_fmm_plan plan, const double* M, const double* com,
                                    const double* gL, double* gM, double* gcom, int sched,

@@ -139,6 +139,11 @@ bool valid_bwd_sched(int s)
 
 constexpr int kCounterSlots = 64;
 
+// default schedule of every full-truncation pass (not autotuned): 8
+// wavefronts in two passes, persistent, in the XCD-aware pieces -- measured
+// 6% faster than one pass of 8 wavefronts for the forward and the adjoint
+constexpr int kFullSched = OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL;
+
 int pick_fwd(int sched, int tuned)
 {
     if (sched == OT_FMM_SCHED_AUTO) sched = tuned ? tuned : OT_FMM_SCHED_W16;
@@ -302,7 +307,7 @@ int fwd_batched(ot_fmm_plan plan, const double* M, const double* com, double* L,
 }
 
 // Forward with the full truncation: the same plan, tables and schedules as
-// the forward (not timed by the plan's events); 8 wavefronts by default.
+// the forward (not timed by the plan's events); kFullSched by default.
 int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, int sched,
                      hipStream_t stream)
 {
@@ -318,7 +323,7 @@ int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
     kp.out_stride = (long)plan->T * kSub3;
     kp.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
-    if (sched == OT_FMM_SCHED_AUTO) sched = OT_FMM_SCHED_W8;
+    if (sched == OT_FMM_SCHED_AUTO) sched = kFullSched;
     const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
     apply_order(kp, plan, sched, false);
     const int shape = sched & kShapeMask;
@@ -331,7 +336,7 @@ int fwd_full_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
 }
 
 // Adjoint of the batched forward (FULL: of the full truncation, with
-// derivatives to order 7; 8 wavefronts by default, 16 refused -- their
+// derivatives to order 7; kFullSched by default, 16 wavefronts refused -- their
 // register budget is far below what the order-7 sums hold -- and not timed
 // by the plan's events).
 template <bool FULL>
@@ -346,10 +351,10 @@ int bwd_any(ot_fmm_plan plan, const double* M, const double* com, const double* 
     // target-role schedule in the low byte, source-role schedule in the next
     int tsched = sched & 0xff, ssched = (sched >> 8) & 0xff;
     if (tsched == OT_FMM_SCHED_AUTO)
-        tsched = FULL ? OT_FMM_SCHED_W8
+        tsched = FULL ? kFullSched
                       : ((plan->tuned_bwd & 0xff) ? (plan->tuned_bwd & 0xff) : OT_FMM_SCHED_W16);
     if (ssched == OT_FMM_SCHED_AUTO)
-        ssched = FULL ? OT_FMM_SCHED_W8 : ((plan->tuned_bwd >> 8) ? (plan->tuned_bwd >> 8) : kDefaultSourceSched);
+        ssched = FULL ? kFullSched : ((plan->tuned_bwd >> 8) ? (plan->tuned_bwd >> 8) : kDefaultSourceSched);
     if (!valid_bwd_sched(tsched | (ssched << 8))) return fail(OT_FMM_EINVAL, "unknown backward schedule");
     if (FULL && (tsched & kShapeMask) == OT_FMM_SCHED_W16)
         return fail(OT_FMM_EINVAL, "16 wavefronts are not available for the full truncation's adjoint");
