@@ -551,8 +551,9 @@ constexpr int lds_doubles()
 // Staging of one source z-plane (the 24 x 24 cells of the 3 x 3 neighbour
 // blocks), one cell per thread: thread v takes cell v & 63 of block v >> 6
 // (the block is wavefront-uniform, so its relation is a scalar load), loads
-// the cell's centre and each of its moments once (every load of a wavefront
-// reads 512 contiguous bytes), forms the scaled trace-reduced sources with
+// the cell's centre and each of its moments once (a load of a wavefront reads
+// 512 contiguous bytes in the batched forms, 8 rows of 64 bytes in the
+// single-block form), forms the scaled trace-reduced sources with
 // compile-time factors, and writes the cell's record with 16-byte LDS
 // stores. A missing neighbour block is staged far away with zero sources.
 template <int MODE, int B>
