@@ -221,3 +221,35 @@ def test_full_caller_captured_graph_replays(ot, fsched, bsched):
         assert torch.equal(L, refL) and torch.equal(gM, refM) and torch.equal(gX, refX), rep
         junk = torch.randn(1 << 20, device="cuda").sum()
         del junk
+
+
+def test_full_config5_default_schedule_sampled(ot):
+    """32^3 sub-grids (16.8M cells), periodic, 20% missing: the full
+    truncation's forward and adjoint in the launch configuration the benchmark
+    times (the default schedule), sampled targets and store sub-grids checked
+    against the oracle's full truncation."""
+    import torch
+    batch, M, X = synthetic.config5()
+    w = synthetic.weights(batch["T"], 2005)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    NS, NT = batch["S"] * SUB3, batch["T"] * SUB3
+    L, gM, gX = _empty(20, NT), _empty(20, NS), _empty(3, NS)
+    plan.multipole_batched_full(Md, Xd, L)
+    plan.multipole_backward_full(Md, Xd, wd, gM, gX)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(L).all()) and bool(torch.isfinite(gM).all()) and bool(torch.isfinite(gX).all())
+    rng = np.random.default_rng(2006)
+    miss = batch["missing_targets"]
+    sel = np.sort(np.concatenate([rng.choice(miss, 2, replace=False),
+                                  rng.choice(np.setdiff1d(np.arange(batch["T"]), miss), 2,
+                                             replace=False)])).astype(np.int32)
+    idx = torch.from_numpy(sel).long().cuda()
+    cols = lambda t: t.reshape(t.shape[0], -1, SUB3)[:, idx].reshape(t.shape[0], -1).cpu().numpy()
+    ref, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True, full=True)
+    print("config5 full L", assert_parity(cols(L), ref, TOL, what="config5 full L", A=A))
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=sel[:3], full=True)
+    sub = torch.from_numpy(sel[:3]).long().cuda()
+    cols3 = lambda t: t.reshape(t.shape[0], -1, SUB3)[:, sub].reshape(t.shape[0], -1).cpu().numpy()
+    print("config5 full gM", assert_parity(cols3(gM), gM_ref, TOL, what="config5 full gM"))
+    print("config5 full gX", assert_parity(cols3(gX), gX_ref, TOL, what="config5 full gX"))
