@@ -97,3 +97,63 @@ def test_two_level_step_matches_the_oracle_chain(periodic, full):
     print("energy", assert_parity(_host(W)[None, :], W_r[None, :], TOL, groups=[[0]], what="energy"))
     # the parent level contributes: without it the fine coefficients differ
     assert np.abs(oracle.l2l(children, Lp_r, Xp_r, X, np.zeros_like(Lf_r))).max() > 0
+
+
+def test_two_level_step_full_size_sampled():
+    """The two-level step at the benchmark's size (32^3 fine sub-grids, 20%
+    missing 1-9 neighbours, every missing neighbour substituted from the 16^3
+    parent level): the whole chain on the GPU, the oracle's chain on the 16
+    children of two sampled parents (upward pass of every parent, since the
+    coarse substitutes read the parents of the missing neighbours). Fine
+    coefficients checked with the A-scaled criterion of the interaction tests
+    (A: term magnitudes of the fine and coarse sums), force and energy with
+    the plain one."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2303_08058_amd as ot
+
+    n = 32
+    fine, M, X = synthetic.config5(n)
+    coarse, octant = synthetic.coarse_tables(n, fine)
+    children = synthetic.octree_children(n)
+    Sp = children.shape[0]
+    parent = synthetic.parent_lattice(n, periodic=True)
+    assert np.array_equal(fine["tgt"], np.arange(fine["S"]))
+
+    # GPU chain, as the benchmark runs it
+    f64 = dict(dtype=torch.float64, device="cuda")
+    dM, dX = _dev(M), _dev(X)
+    tree = ot.Tree(children, fine["S"])
+    Mp, Xp = torch.empty((20, Sp * SUB3), **f64), torch.empty((3, Sp * SUB3), **f64)
+    tree.m2m(dM, dX, Mp, Xp)
+    plan_f = ot.Plan.from_batch(fine)
+    plan_f.set_coarse(Sp, coarse, octant)
+    Lf = torch.empty((20, fine["T"] * SUB3), **f64)
+    plan_f.multipole_batched(dM, dX, Lf)
+    plan_f.coarse_fine(dX, Mp, Xp, Lf)
+    plan_p = ot.Plan.from_batch(parent)
+    Lp = torch.empty((20, parent["T"] * SUB3), **f64)
+    plan_p.multipole_batched(Mp, Xp, Lp)
+    tree.l2l(Lp, Xp, dX, Lf)
+    F = torch.empty((3, fine["S"] * SUB3), **f64)
+    W = torch.empty((fine["S"] * SUB3,), **f64)
+    ot.ot_fmm_evaluate(dM, Lf, F, W)
+    torch.cuda.synchronize()
+
+    # oracle chain on two sampled parents and their children
+    psel = np.sort(np.random.default_rng(97).choice(Sp, 2, replace=False)).astype(np.int32)
+    kids = children[psel].reshape(-1).astype(np.int32)          # child k of parent q: 8 q + k
+    kcols = (kids[:, None].astype(np.int64) * SUB3 + np.arange(SUB3)).reshape(-1)
+    pcols = (psel[:, None].astype(np.int64) * SUB3 + np.arange(SUB3)).reshape(-1)
+    Mp_r, Xp_r = oracle.m2m(children, M, X)
+    Lf_f, A_f = oracle.batched_forward(fine, M, X, tsel=kids, want_abs=True)
+    Lf_c, A_c = oracle.coarse_fine(fine, X, coarse, octant, Mp_r, Xp_r, tsel=kids, want_abs=True)
+    Lp_r = oracle.batched_forward(parent, Mp_r, Xp_r, tsel=psel)
+    Lf_r = oracle.l2l(np.arange(len(kids), dtype=np.int32).reshape(-1, 8), Lp_r, Xp_r[:, pcols],
+                      X[:, kcols], Lf_f + Lf_c)
+    F_r, W_r = oracle.evaluate(M[:, kcols], Lf_r)
+
+    got = lambda t: t[..., torch.from_numpy(kcols).cuda()].cpu().numpy()
+    print("fine", assert_parity(got(Lf), Lf_r, TOL, what="fine coefficients", A=A_f + A_c))
+    print("force", assert_parity(got(F), F_r, TOL, what="force"))
+    print("energy", assert_parity(got(W)[None, :], W_r[None, :], TOL, groups=[[0]], what="energy"))
