@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--full-steps", type=int, default=2,
                     help="timed launches of the full-truncation forward (0: skip)")
     ap.add_argument("--full-sched", type=lambda v: int(v, 0), default=None,
-                    help="schedule of the full-truncation forward (default: fastest of W8, W8+local, W8P2)")
+                    help="schedule of the full-truncation forward (default: fastest of the library default W8P2+persistent+xcd-local, W8 and W8P2)")
     ap.add_argument("--no-two-level", action="store_true",
                     help="skip the two-level step (its parent-level forward shares the forward kernel)")
     ap.add_argument("--fwd-sched", type=lambda v: int(v, 0), default=None,
