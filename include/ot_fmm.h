@@ -73,9 +73,13 @@ enum {
     OT_FMM_SCHED_W8P2 = 3,  /* 8 wavefronts, two passes over the source planes (target
                                planes 0-3, then 4-7), two wavefronts per target plane */
     /* flag, OR-ed into a schedule: persistent launch -- as many work-groups as
-     * are resident at once, taking work-list entries (longest first) from a
-     * counter that a one-thread kernel zeroes just before; up to 64 such
-     * launches of one plan may be in flight at once */
+     * are resident at once, taking work-list entries (longest first) from
+     * counters that a one-thread kernel zeroes just before, on the same
+     * stream. The counters are never shared by launches that can overlap:
+     * eager launches use one set per stream (up to 64 streams per plan),
+     * launches recorded into a graph a set of their own (up to 960 per plan
+     * over its life; the plan's own step graph returns its sets when it is
+     * replaced). Beyond either limit the call returns OT_FMM_EINVAL. */
     OT_FMM_SCHED_PERSISTENT = 0x10,
     /* flag, OR-ed into a schedule: XCD-aware work order -- entries sorted
      * along a Morton curve of the lattice positions recovered from the

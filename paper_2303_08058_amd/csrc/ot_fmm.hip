@@ -137,7 +137,19 @@ bool valid_bwd_sched(int s)
     return valid_fwd_sched(t) && valid_fwd_sched(r) && (r & kShapeMask) != OT_FMM_SCHED_W16;
 }
 
-constexpr int kCounterSlots = 64;
+// Work counters of persistent launches. Each launch takes a slot of
+// kMaxPieces counters that no launch able to run at the same time shares:
+//  * eager launches: one slot per stream -- launches on one stream run in
+//    order, each preceded on that stream by the kernel that zeroes its slot
+//    (kEagerSlots streams per plan);
+//  * launches recorded into a graph (the stream is capturing): a slot of
+//    their own that no other launch is given, since the graph may be
+//    replayed at any time until it is destroyed, which the library cannot
+//    see (kCaptureSlots per plan); the slots of the plan's own step graph
+//    return to the pool when that graph is replaced.
+constexpr int kEagerSlots = 64;
+constexpr int kCaptureSlots = 960;
+constexpr int kCounterSlots = kEagerSlots + kCaptureSlots;
 
 // default schedule of every full-truncation pass (not autotuned): 8
 // wavefronts in two passes, persistent, in the XCD-aware pieces -- measured
@@ -174,10 +186,17 @@ struct ot_fmm_plan_s {
     int fwd_piece_off[kMaxPieces + 1] = {0};
     int rev_piece_off[kMaxPieces + 1] = {0};
     int tuned_fwd = 0, tuned_bwd = 0;
-    // persistent launches: one set of kMaxPieces work counters per launch in
-    // flight (rotating)
+    // persistent launches: kMaxPieces work counters per slot; slots
+    // [0, kEagerSlots) belong to streams (eager launches), the others to
+    // launches recorded into graphs (see counter_slot)
     int* d_counters = nullptr;  // [kCounterSlots][kMaxPieces]
-    std::atomic<unsigned> next_counter{0};
+    std::mutex slot_mutex;
+    std::vector<std::pair<hipStream_t, int>> stream_slot;  // eager: stream -> slot
+    int next_capture = 0;                  // capture slots handed out so far
+    std::vector<int> free_capture;         // capture slots returned by replaced step graphs
+    std::vector<int> graph_slots;          // capture slots of the plan's step graph
+    std::vector<int>* capture_log = nullptr;  // collects them while it is captured
+    hipStream_t capture_stream = nullptr;     // on this stream
     int n_cu = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -239,18 +258,59 @@ int resident_per_cu()
     return n;
 }
 
+// The counter slot of a persistent launch on `stream` (kEagerSlots /
+// kCaptureSlots rules above).
+int counter_slot(ot_fmm_plan plan, hipStream_t stream, int** out)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    OT_HIP(hipStreamIsCapturing(stream, &st));
+    std::lock_guard<std::mutex> lock(plan->slot_mutex);
+    int slot = -1;
+    if (st != hipStreamCaptureStatusNone) {
+        if (!plan->free_capture.empty()) {
+            slot = plan->free_capture.back();
+            plan->free_capture.pop_back();
+        } else if (plan->next_capture < kCaptureSlots) {
+            slot = kEagerSlots + plan->next_capture++;
+        } else {
+            return fail(OT_FMM_EINVAL, "more persistent launches recorded into graphs than the plan's "
+                                       "960 counter slots; use a non-persistent schedule or a new plan");
+        }
+        if (plan->capture_log && stream == plan->capture_stream) plan->capture_log->push_back(slot);
+    } else {
+        for (const auto& e : plan->stream_slot)
+            if (e.first == stream) {
+                slot = e.second;
+                break;
+            }
+        if (slot < 0) {
+            if ((int)plan->stream_slot.size() >= kEagerSlots)
+                return fail(OT_FMM_EINVAL, "persistent launches of one plan on more than 64 streams; use a "
+                                           "non-persistent schedule or another plan");
+            slot = (int)plan->stream_slot.size();
+            plan->stream_slot.emplace_back(stream, slot);
+        }
+    }
+    *out = plan->d_counters + (size_t)slot * kMaxPieces;
+    return OT_FMM_OK;
+}
+
 // One launch over `nblocks` work-list entries: a work-group per entry, or
 // (persistent) as many work-groups as fit the device at once, each taking
-// entries from a zeroed counter slot of the plan.
+// entries from a counter slot of the plan, zeroed just before on the stream.
 template <int MODE, int NW, int NP = 1>
 int launch_timed(ot_fmm_plan plan, int which, KParams kp, int nblocks, bool persistent,
                  hipStream_t stream)
 {
+    int* c = nullptr;
+    if (persistent && nblocks > 0) {
+        const int rs = counter_slot(plan, stream, &c);
+        if (rs) return rs;
+    }
     std::pair<hipEvent_t, hipEvent_t> ev;
     int rc = timing_begin(plan, which, stream, &ev);
     if (rc) return rc;
     if (persistent && nblocks > 0) {
-        int* c = plan->d_counters + (size_t)(plan->next_counter.fetch_add(1) % kCounterSlots) * kMaxPieces;
         hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(kMaxPieces), 0, stream, c);
         kp.counter = c;
         kp.n_items = nblocks;
@@ -1237,26 +1297,60 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     }
     const bool timing = plan->timing;
     plan->timing = false;  // no timing events inside the graph
+    std::vector<int> slots;  // counter slots the captured launches take
+    {
+        std::lock_guard<std::mutex> lock(plan->slot_mutex);
+        plan->capture_log = &slots;
+        plan->capture_stream = cs;
+    }
     rc = fwd_batched(plan, M, com, L, fwd_sched, cs);
     if (!rc && with_bwd) rc = bwd_batched(plan, M, com, gL, gM, gcom, bwd_sched, cs);
     plan->timing = timing;
+    {
+        std::lock_guard<std::mutex> lock(plan->slot_mutex);
+        plan->capture_log = nullptr;
+        plan->capture_stream = nullptr;
+    }
+    // slots of a graph that is never instantiated go back to the pool
+    auto give_back = [&](const std::vector<int>& v) {
+        std::lock_guard<std::mutex> lock(plan->slot_mutex);
+        plan->free_capture.insert(plan->free_capture.end(), v.begin(), v.end());
+    };
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
     if (rc) {
         if (g) (void)hipGraphDestroy(g);
+        give_back(slots);
         return rc;
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    if (e != hipSuccess) {
+        give_back(slots);
+        return hip_fail(e, "hipStreamEndCapture");
+    }
     hipGraphExec_t ex = nullptr;
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g);
+        give_back(slots);
         return hip_fail(e, "hipGraphInstantiate");
     }
-    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->graph_exec) {
+        // a replay of the graph being replaced may still run: its counter
+        // slots are reused only once the device is idle
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            (void)hipGraphDestroy(g);
+            give_back(slots);
+            return hip_fail(e, "hipDeviceSynchronize");
+        }
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        give_back(plan->graph_slots);
+    }
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     plan->graph = g;
     plan->graph_exec = ex;
+    plan->graph_slots.swap(slots);
     return OT_FMM_OK;
 }
 
