@@ -1,17 +1,20 @@
 """Parity criterion shared by the GPU tests.
 
-For every sub-grid and every group of components (the 20 outputs grouped by
-order 0..3; the 3 position-gradient components as one group):
-    max |got - ref| <= tol * D,    D = max |ref|  over that sub-grid's cells.
+Gate, for every sub-grid and every group of components (the 20 outputs
+grouped by order 0..3; the 3 position-gradient components as one group):
+    max |got - ref| <= tol * max |ref|      over that sub-grid's cells.
 Componentwise relative error is not used: components that cancel (e.g. a
 dipole-like output on a symmetry plane) have no meaningful relative error.
 
-Where the oracle also supplies A, the sum of the magnitudes of the terms of
-each output, the denominator is D = max(max|ref|, 1e-2 * max A): in sub-grids
-whose outputs cancel by more than a factor of 100 (near-uniform density
-regions, measured up to ~600 for second-order outputs), 1e-12 of max|ref|
-would be below the FP64 rounding noise of any reordered sum of the same
-terms; there the bound is 1e-14 of the term magnitudes instead.
+Cancellation fallback. Where the oracle also supplies A, the sum of the
+magnitudes of the terms of each output, a group whose outputs cancel by more
+than a factor of 100 (max |ref| < 1e-2 max A; measured up to ~600 for
+second-order outputs in near-uniform regions) that misses the bound above
+passes if max |got - ref| <= tol * 1e-2 * max A: there any FP64 sum of the
+same terms in another order differs from the oracle's by ~1e-15 of A, which
+can exceed 1e-12 of max |ref|. Groups that cancel less than that are held to
+the plain bound whatever A is. Every check prints how many groups cancel by
+more than 100 and how many needed the fallback, with the worst plain ratio.
 """
 import numpy as np
 
@@ -19,7 +22,16 @@ ORDER_GROUPS_20 = [[0], [1, 2, 3], list(range(4, 10)), list(range(10, 20))]
 GROUPS_3 = [[0, 1, 2]]
 
 
+def _ratio(err, scale):
+    return np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), np.where(err > 0, np.inf, 0.0))
+
+
 def parity_report(got, ref, tol=1e-12, groups=None, A=None):
+    """Per (group, sub-grid) ratios. Returns a dict: worst (gate ratio after the
+    fallback), worst_plain, groups (number checked), cancelling (groups with
+    max|ref| < 1e-2 max A), fallback (groups that passed only through A),
+    worst_plain_fallback (their worst plain ratio), bad (first failures as
+    (first component, sub-grid, ratio))."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
     assert got.shape == ref.shape, (got.shape, ref.shape)
@@ -28,32 +40,40 @@ def parity_report(got, ref, tol=1e-12, groups=None, A=None):
     if groups is None:
         groups = ORDER_GROUPS_20 if ncomp == 20 else GROUPS_3
     nsub = n // 512
-    worst = 0.0
-    worst_plain = 0.0
-    bad = []
+    rep = {"worst": 0.0, "worst_plain": 0.0, "groups": 0, "cancelling": 0, "fallback": 0,
+           "worst_plain_fallback": 0.0, "bad": []}
     for g in groups:
         r = ref[g].reshape(len(g), nsub, 512)
         d = np.abs(got[g].reshape(len(g), nsub, 512) - r)
         scale = np.abs(r).max(axis=(0, 2))
         err = d.max(axis=(0, 2))
-        plain = np.where(scale > 0, err / np.where(scale > 0, scale, 1.0),
-                         np.where(err > 0, np.inf, 0.0))
-        worst_plain = max(worst_plain, float(plain.max()))
+        plain = _ratio(err, scale)
+        gate = plain.copy()
+        rep["groups"] += nsub
+        rep["worst_plain"] = max(rep["worst_plain"], float(plain.max()))
         if A is not None:
-            a = np.asarray(A, np.float64)[g].reshape(len(g), nsub, 512).max(axis=(0, 2))
-            scale = np.maximum(scale, 1e-2 * a)
-        ratio = np.where(scale > 0, err / np.where(scale > 0, scale, 1.0),
-                         np.where(err > 0, np.inf, 0.0))
-        worst = max(worst, float(ratio.max()))
-        for s in np.nonzero(ratio > tol)[0][:5]:
-            bad.append((g[0], int(s), float(ratio[s])))
-    return worst, worst_plain, bad
+            a = 1e-2 * np.asarray(A, np.float64)[g].reshape(len(g), nsub, 512).max(axis=(0, 2))
+            cancel = scale < a
+            rep["cancelling"] += int(np.count_nonzero(cancel))
+            alt = _ratio(err, a)
+            use = cancel & (plain > tol) & (alt <= tol)
+            rep["fallback"] += int(np.count_nonzero(use))
+            if use.any():
+                rep["worst_plain_fallback"] = max(rep["worst_plain_fallback"], float(plain[use].max()))
+            gate = np.where(cancel, np.minimum(plain, alt), plain)
+        rep["worst"] = max(rep["worst"], float(gate.max()))
+        for s in np.nonzero(gate > tol)[0][:5]:
+            rep["bad"].append((g[0], int(s), float(gate[s])))
+    return rep
 
 
 def assert_parity(got, ref, tol=1e-12, groups=None, what="", A=None):
-    worst, worst_plain, bad = parity_report(got, ref, tol, groups, A)
-    assert not bad, "%s: parity %.3e > %.1e at (first comp, sub-grid, ratio) %s" % (
-        what, worst, tol, bad)
+    rep = parity_report(got, ref, tol, groups, A)
+    assert not rep["bad"], "%s: parity %.3e > %.1e at (first comp, sub-grid, ratio) %s" % (
+        what, rep["worst"], tol, rep["bad"])
     if A is not None:
-        print("%s: worst %.2e (plain max|ref| denominator: %.2e)" % (what, worst, worst_plain))
-    return worst
+        print("%s: %d (sub-grid, order) groups, worst plain ratio %.2e; cancelling > 100x: %d; "
+              "passed through the fallback: %d (worst plain ratio there %.2e)"
+              % (what, rep["groups"], rep["worst_plain"], rep["cancelling"], rep["fallback"],
+                 rep["worst_plain_fallback"]), flush=True)
+    return rep["worst"]
