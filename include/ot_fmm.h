@@ -368,6 +368,44 @@ int ot_fmm_future_wait(ot_fmm_future f, double timeout_s);
 int ot_fmm_future_release(ot_fmm_future f);
 
 /* ---------------------------------------------------------------------------
+ * Allocation-free batched forward, for callers that cannot allocate device
+ * memory or create a plan: code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.
+ *
+ * The result of ot_fmm_multipole_batched with the schedule
+ * W16 | PERSISTENT (bitwise), without a plan. The descriptor (same meaning as
+ * for ot_fmm_plan_create) is given in DEVICE arrays owned by the caller:
+ * tgt[T] and nbr[T][27] (int32, 4-byte aligned), shift[T][27][3] (int8) or
+ * NULL; period[3] is a HOST array (may be NULL when shift is NULL). M, com, L
+ * as for ot_fmm_multipole_batched (L[20][T*512] overwritten).
+ *
+ * Scratch memory: the call's relation table and the work counters live in one
+ * fixed library array per device (13.6 MiB, taken on the first call on a
+ * device and held until the process ends); T <= OT_FMM_NOALLOC_MAX_T, EINVAL
+ * beyond (nothing enqueued). The call allocates nothing and only enqueues
+ * kernels on `stream` (it may be captured). Every call on a device shares
+ * that array, which keeps the last call's contents: calls that can overlap on
+ * one device (other streams or threads, replays of graphs holding a call) race
+ * and must be ordered by the caller.
+ *
+ * Errors: host-side checks as for the other entry points (EINVAL, nothing
+ * enqueued). The table entries are checked on the device: an entry out of
+ * range (tgt outside [0, S), nbr outside [-1, S), nbr[t][13] != tgt[t]) is
+ * dropped and counted, and then every element of L is set to NaN;
+ * ot_fmm_noalloc_status returns the count. Unlike a plan, repeated target
+ * ids are not rejected (the forward does not need them distinct).
+ * ------------------------------------------------------------------------- */
+#define OT_FMM_NOALLOC_MAX_T 32768
+int ot_fmm_multipole_batched_noalloc(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr,
+                                     const int8_t* shift, const double* period, const double* M,
+                                     const double* com, double* L, void* stream);
+
+/* Descriptor check of the last allocation-free call on the current device:
+ * waits for the device, then returns the number of invalid entries and the
+ * first of them (t * 27 + slot; INT32_MAX when there is none). Synchronous. */
+int ot_fmm_noalloc_status(int32_t* invalid, int32_t* first_invalid);
+
+/* ---------------------------------------------------------------------------
  * Helpers
  * ------------------------------------------------------------------------- */
 const char* ot_fmm_strerror(int code);

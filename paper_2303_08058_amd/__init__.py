@@ -91,6 +91,10 @@ _lib.ot_fmm_plan_timing.argtypes = [_P, _I]
 _lib.ot_fmm_plan_timing.restype = _I
 _lib.ot_fmm_plan_kernel_times.argtypes = [_P, _P, _P]
 _lib.ot_fmm_plan_kernel_times.restype = _I
+_lib.ot_fmm_multipole_batched_noalloc.argtypes = [_I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P]
+_lib.ot_fmm_multipole_batched_noalloc.restype = _I
+_lib.ot_fmm_noalloc_status.argtypes = [ctypes.POINTER(_I32), ctypes.POINTER(_I32)]
+_lib.ot_fmm_noalloc_status.restype = _I
 
 _lib.ot_fmm_tree_create.argtypes = [_I32, _I32, _P, ctypes.POINTER(_P)]
 _lib.ot_fmm_tree_create.restype = _I
@@ -381,6 +385,50 @@ def ot_fmm_coarse_fine(plan, com, Mp, comp, L, stream=None):
 
 def ot_fmm_coarse_fine_full(plan, com, Mp, comp, L, stream=None):
     return plan.coarse_fine(com, Mp, comp, L, stream, full=True)
+
+
+NOALLOC_MAX_T = 32768
+
+
+def _iptr(t, shape, dtype, name):
+    """Device pointer of a contiguous integer GPU tensor of the given shape and dtype."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda" or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s GPU tensor" % (name, dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def ot_fmm_multipole_batched_noalloc(S, T, tgt, nbr, shift, period, M, com, L, stream=None):
+    """Allocation-free batched forward (no plan): tgt (T,) and nbr (T, 27)
+    int32 GPU tensors, shift (T, 27, 3) int8 GPU tensor or None, period three
+    floats or None; M (20, S*512), com (3, S*512) -> L (20, T*512)."""
+    S, T = int(S), int(T)
+    per = None
+    if period is not None:
+        per = np.ascontiguousarray(period, dtype=np.float64)
+        if per.shape != (3,):
+            raise ValueError("period must be (3,)")
+    _check(_lib.ot_fmm_multipole_batched_noalloc(
+        S, T, _iptr(tgt, (T,), torch.int32, "tgt"), _iptr(nbr, (T, 27), torch.int32, "nbr"),
+        _iptr(shift, (T, 27, 3), torch.int8, "shift"),
+        None if per is None else per.ctypes.data_as(_P),
+        _dptr(M, (20, S * 512), "M"), _dptr(com, (3, S * 512), "com"), _dptr(L, (20, T * 512), "L"),
+        _stream(stream)), "ot_fmm_multipole_batched_noalloc")
+    return L
+
+
+def ot_fmm_noalloc_status():
+    """(invalid descriptor entries, first invalid entry) of the last
+    allocation-free call on the current device (waits for the device)."""
+    n = _I32()
+    first = _I32()
+    _check(_lib.ot_fmm_noalloc_status(ctypes.byref(n), ctypes.byref(first)), "ot_fmm_noalloc_status")
+    return int(n.value), int(first.value)
 
 
 class MultipoleBatched(torch.autograd.Function):

@@ -1396,3 +1396,195 @@ int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launc
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Allocation-free batched forward (ot_fmm_multipole_batched_noalloc)
+// ===========================================================================
+namespace {
+
+constexpr int kNoAllocMaxT = OT_FMM_NOALLOC_MAX_T;
+constexpr int kNoAllocDevices = 64;
+// Layout of `scratch`, in int4 units: [0, kScrHead) the header -- ints
+// 0..15 the work counters of the persistent launch, int 16 the number of
+// invalid descriptor entries, int 17 the first of them; then the targets'
+// own store blocks (kNoAllocMaxT ints); then the relation table [T][27].
+constexpr long kScrHead = 16;
+constexpr long kScrOwn = kNoAllocMaxT / 4;
+constexpr long kScrInt4 = kScrHead + kScrOwn + 27L * kNoAllocMaxT;
+static_assert(kMaxPieces <= 16, "counters fit the header");
+
+// The scratch memory of the allocation-free entry point: one copy per device,
+// held until the process ends. Host code passes the address that
+// hipGetSymbolAddress returns for it, never this name.
+static __device__ __align__(256) int4 scratch[kScrInt4];
+
+std::mutex g_scratch_mutex;
+int4* g_scratch_ptr[kNoAllocDevices];  // per device, set once
+int g_scratch_ncu[kNoAllocDevices];
+
+// This device's copy of `scratch` and its CU count, looked up on the first
+// call on the device (with the device current) and kept.
+int scratch_of_current_device(int4** base, int* ncu)
+{
+    int dev = 0;
+    OT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(OT_FMM_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        OT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255u))
+            return fail(OT_FMM_EHIP, "scratch array address not 256-byte aligned");
+        int n = 0;
+        OT_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        g_scratch_ncu[dev] = n > 0 ? n : 1;
+        g_scratch_ptr[dev] = static_cast<int4*>(ptr);
+    }
+    *base = g_scratch_ptr[dev];
+    *ncu = g_scratch_ncu[dev];
+    return OT_FMM_OK;
+}
+
+// Clears the header: the work counters and the invalid-entry count start at
+// zero, the first invalid entry at INT_MAX (a kernel, so that graph captures
+// hold no memset node).
+__global__ void k_noalloc_reset(int* head)
+{
+    const int t = threadIdx.x;
+    if (t < 16) head[t] = 0;
+    if (t == 16) head[16] = 0;
+    if (t == 17) head[17] = 0x7fffffff;
+}
+
+// Relation table of the call from the caller's device descriptor, checked
+// entry by entry: an entry out of range is dropped (stored as missing, its
+// target's own block as 0) and counted.
+__global__ void __launch_bounds__(256) k_noalloc_relations(int S, int T, const int* __restrict__ tgt,
+                                                           const int* __restrict__ nbr,
+                                                           const int8_t* __restrict__ shift, int* own,
+                                                           int4* rel, int* status)
+{
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= T * 27) return;
+    const int t = i / 27, s = i - 27 * t;
+    const int ob = tgt[t];
+    const bool own_ok = ob >= 0 && ob < S;
+    int b = nbr[i];
+    const bool ok = own_ok && b >= -1 && b < S && (s != 13 || b == ob);
+    int packed = 0;
+    if (shift)
+        for (int k = 0; k < 3; ++k) packed |= ((int)shift[3 * i + k] & 0xff) << (8 * k);
+    if (!ok) {
+        atomicAdd(status, 1);
+        atomicMin(status + 1, i);
+        b = -1;
+    }
+    rel[i] = make_int4(b, b, packed, 0);
+    if (s == 13) own[t] = own_ok ? ob : 0;
+}
+
+// After a call with invalid entries every element of L becomes NaN.
+__global__ void __launch_bounds__(256) k_noalloc_poison(const int* status, double* L, long n)
+{
+    if (status[0] == 0) return;
+    const double nan = __builtin_nan("");
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) L[i] = nan;
+}
+
+// Do the byte ranges [a, a + na) and [b, b + nb) share memory?
+bool overlap_bytes(const void* a, size_t na, const void* b, size_t nb)
+{
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a && b && a0 < b0 + nb && b0 < a0 + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ot_fmm_multipole_batched_noalloc(int32_t S, int32_t T, const int32_t* tgt, const int32_t* nbr,
+                                     const int8_t* shift, const double* period, const double* M,
+                                     const double* com, double* L, void* stream)
+{
+    g_last_error.clear();
+    if (S <= 0 || T <= 0) return fail(OT_FMM_EINVAL, "S and T must be positive");
+    if (T > kNoAllocMaxT)
+        return fail(OT_FMM_EINVAL, "T exceeds the 32768 targets of the allocation-free scratch array "
+                                   "(use a plan: ot_fmm_plan_create)");
+    if ((int64_t)S * kSub3 * 20 > ((int64_t)1 << 40)) return fail(OT_FMM_EINVAL, "store too large");
+    if (!tgt || !nbr || (reinterpret_cast<uintptr_t>(tgt) & 3u) || (reinterpret_cast<uintptr_t>(nbr) & 3u))
+        return fail(OT_FMM_EINVAL, "null or misaligned (4-byte) tgt or nbr");
+    if (shift && !period) return fail(OT_FMM_EINVAL, "shift given without period");
+    double per[3] = {0.0, 0.0, 0.0};
+    if (period)
+        for (int k = 0; k < 3; ++k) {
+            if (!(period[k] == period[k]) || period[k] > 1e15 || period[k] < -1e15)
+                return fail(OT_FMM_EINVAL, "period must be finite");
+            per[k] = period[k];
+        }
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)S * kSub3, NT = (int64_t)T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    const size_t nL = (size_t)(20 * NT) * sizeof(double);
+    if (overlap_bytes(L, nL, tgt, (size_t)T * 4) || overlap_bytes(L, nL, nbr, (size_t)T * 27 * 4) ||
+        overlap_bytes(L, nL, shift, (size_t)T * 27 * 3))
+        return fail(OT_FMM_EINVAL, "L overlaps the descriptor");
+    int rc = ensure_device();
+    if (rc) return rc;
+    int4* base = nullptr;
+    int ncu = 1;
+    if ((rc = scratch_of_current_device(&base, &ncu))) return rc;
+    int* head = reinterpret_cast<int*>(base);
+    int* own = reinterpret_cast<int*>(base + kScrHead);
+    int4* rel = base + kScrHead + kScrOwn;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_noalloc_reset, dim3(1), dim3(64), 0, s, head);
+    hipLaunchKernelGGL(k_noalloc_relations, dim3((unsigned)((T * 27 + 255) / 256)), dim3(256), 0, s, (int)S,
+                       (int)T, tgt, nbr, shift, own, rel, head + 16);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    // the forward of ot_fmm_multipole_batched with W16 | PERSISTENT, work
+    // entries in target order from the scratch counter
+    KParams kp{};
+    kp.mom = M;
+    kp.pos = com;
+    kp.mom_stride = NS;
+    kp.pos_stride = NS;
+    kp.rel = rel;
+    kp.own_blk = own;
+    kp.order = nullptr;
+    kp.out0 = L;
+    kp.out_stride = NT;
+    kp.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) kp.period[k] = per[k];
+    kp.counter = head;
+    kp.n_items = T;
+    kp.npieces = 0;
+    const long resident = (long)ncu * resident_per_cu<MODE_FWD_STORE, 16, 1>();
+    const int nblocks = (int)std::min<long>(T, resident);
+    if ((rc = launch<MODE_FWD_STORE, 16, false, 1, true>(kp, nblocks, s))) return rc;
+    hipLaunchKernelGGL(k_noalloc_poison, dim3(1024), dim3(256), 0, s, head + 16, L, (long)(20 * NT));
+    e = hipGetLastError();
+    return e == hipSuccess ? OT_FMM_OK : hip_fail(e, "kernel launch");
+}
+
+int ot_fmm_noalloc_status(int32_t* invalid, int32_t* first_invalid)
+{
+    g_last_error.clear();
+    if (!invalid || !first_invalid) return fail(OT_FMM_EINVAL, "null argument");
+    int rc = ensure_device();
+    if (rc) return rc;
+    int4* base = nullptr;
+    int ncu = 1;
+    if ((rc = scratch_of_current_device(&base, &ncu))) return rc;
+    OT_HIP(hipDeviceSynchronize());
+    int st[2] = {0, 0};
+    OT_HIP(hipMemcpy(st, reinterpret_cast<int*>(base) + 16, sizeof(st), hipMemcpyDeviceToHost));
+    *invalid = st[0];
+    *first_invalid = st[1];
+    return OT_FMM_OK;
+}
+
+}  // extern "C"
