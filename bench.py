@@ -50,6 +50,12 @@ FLOP_PER_PAIR = {
     "forward": 61 + 2 * 84,                # 229
     "adjoint_source": 121 + 2 * (84 + 111),  # 511
     "adjoint_target": 121 + 2 * (64 + 111),  # 471
+    # the two-launch step: the forward that saves the target-side sums
+    # evaluates the order-4 derivatives, the forward contraction (84 FMA) and
+    # the order-4 terms of orders 1..4 (111 FMA); the one-pass adjoint is the
+    # source-role pass (its per-cell epilogue adds the target role)
+    "forward_save": 121 + 2 * (84 + 111),    # 511
+    "adjoint_saved": 121 + 2 * (84 + 111),   # 511
 }
 
 
@@ -113,6 +119,10 @@ def main():
                     help="forward schedule code (skips the autotuner; e.g. 0x22 = W16 + XCD-local order)")
     ap.add_argument("--bwd-sched", type=lambda v: int(v, 0), default=None,
                     help="backward schedule code, target role | source role << 8 (with --fwd-sched)")
+    ap.add_argument("--save-sched", type=lambda v: [int(x, 0) for x in v.split(",")], default=None,
+                    help="schedules of the two-launch step, forward,adjoint (skips its autotuner; e.g. 0x33,0x33)")
+    ap.add_argument("--no-two-pass", action="store_true",
+                    help="skip the three-launch step (plain forward, two adjoint passes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counters)")
     args = ap.parse_args()
@@ -150,59 +160,102 @@ def main():
     torch.cuda.synchronize()
     log("plan: %d targets, %d pairs" % (batch["T"], pairs))
 
-    if args.fwd_sched is not None and args.bwd_sched is not None:
-        fs, bs = args.fwd_sched, args.bwd_sched
+    def time_step():
+        for _ in range(args.warmup):
+            plan.step_graph_launch()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        e0.record(stream)
+        for i in range(args.steps):
+            plan.step_graph_launch()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        return e0.elapsed_time(e1) / args.steps, wall * 1e3 / args.steps
+
+    def kernel_stats(kt):
+        out = {}
+        for k, (ms, n) in kt.items():
+            if n == 0:
+                continue
+            mean = ms / n
+            out[k] = {"mean_ms": round(mean, 4), "launches": n,
+                      "impl_tflops": round(pairs * FLOP_PER_PAIR[k] / (mean * 1e-3) / 1e12, 3),
+                      "impl_flop_per_pair": FLOP_PER_PAIR[k]}
+            log("kernel %-15s %.3f ms  %.2f TFLOP/s (implementation count)" % (k, mean, out[k]["impl_tflops"]))
+        return out
+
+    kernels = {}
+    two_pass = None
+    fs = bs = None
+    if not args.no_two_pass:
+        # three-launch step: plain forward, source- and target-role adjoint passes
+        if args.fwd_sched is not None and args.bwd_sched is not None:
+            fs, bs = args.fwd_sched, args.bwd_sched
+        else:
+            fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
+        log("three-launch step: forward %s, adjoint target role %s, source role %s"
+            % (sched_name(fs), sched_name(bs & 0xff), sched_name(bs >> 8)))
+        plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
+        ms_two, wall_two = time_step()
+        log("three-launch graph step: %.2f ms (wall %.2f ms)" % (ms_two, wall_two))
+        plan.set_timing(True)
+        plan.kernel_times()
+        for i in range(args.steps):
+            plan.multipole_batched(Md, Xd, L, sched=fs)
+            plan.multipole_backward(Md, Xd, wd, gM, gX, sched=bs)
+        kernels.update(kernel_stats(plan.kernel_times()))
+        plan.set_timing(False)
+        adj2_ms = kernels["adjoint_source"]["mean_ms"] + kernels["adjoint_target"]["mean_ms"]
+        two_pass = {
+            "ms_per_step": round(ms_two, 3), "pairs_per_s": pairs / (ms_two * 1e-3),
+            "schedules": {"forward": sched_name(fs), "adjoint_target": sched_name(bs & 0xff),
+                          "adjoint_source": sched_name(bs >> 8)},
+            "fwd_bwd_frac_fp64_peak": round(pairs * METHOD_FLOP["step"] / (ms_two * 1e-3) / 1e12
+                                            / PEAK_FP64_TFLOPS, 4),
+            "adjoint_ms": round(adj2_ms, 3),
+            "adjoint_frac_fp64_peak": round(pairs * METHOD_FLOP["adjoint"] / (adj2_ms * 1e-3) / 1e12
+                                            / PEAK_FP64_TFLOPS, 4),
+        }
+
+    # two-launch step (the timed step): the forward that saves the target-side
+    # sums, and the one-pass adjoint that uses them
+    Cs = torch.empty((ot.NSAVED, NT), dtype=torch.float64, device=dev)
+    if args.save_sched is not None:
+        sf, sb = args.save_sched
     else:
-        fs, bs = plan.autotune(Md, Xd, L, wd, gM, gX)
-    log("autotuned schedules: forward %s, adjoint target role %s, source role %s"
-        % (sched_name(fs), sched_name(bs & 0xff), sched_name(bs >> 8)))
-    plan.step_graph_create(Md, Xd, L, wd, gM, gX, fs, bs)
-
-    # ------------------------------------------------------------ timed steps
-    for _ in range(args.warmup):
-        plan.step_graph_launch()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    e0.record(stream)
-    for i in range(args.steps):
-        plan.step_graph_launch()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    log("graph step: %.2f ms (wall %.2f ms)" % (ms_per_step, wall * 1e3 / args.steps))
-
-    # per-kernel durations: the same step as direct launches, HIP events on the
-    # launch stream around every kernel
+        sf, sb = plan.autotune_saved(Md, Xd, L, Cs, wd, gM, gX)
+    log("two-launch step: forward with saved sums %s, one-pass adjoint %s" % (sched_name(sf), sched_name(sb)))
+    plan.step_graph_create_saved(Md, Xd, L, Cs, wd, gM, gX, sf, sb)
+    ms_per_step, wall_step = time_step()
+    log("two-launch graph step: %.2f ms (wall %.2f ms)" % (ms_per_step, wall_step))
     plan.set_timing(True)
     plan.kernel_times()
     for i in range(args.steps):
-        plan.multipole_batched(Md, Xd, L, sched=fs)
-        plan.multipole_backward(Md, Xd, wd, gM, gX, sched=bs)
-    kt = plan.kernel_times()
+        plan.multipole_batched_save(Md, Xd, L, Cs, sched=sf)
+        plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, sched=sb)
+    kernels.update(kernel_stats(plan.kernel_times()))
     plan.set_timing(False)
-    kernels = {}
-    for k, (ms, n) in kt.items():
-        mean = ms / max(n, 1)
-        fl = pairs * FLOP_PER_PAIR[k]
-        kernels[k] = {"mean_ms": round(mean, 4), "launches": n,
-                      "impl_tflops": round(fl / (mean * 1e-3) / 1e12, 3),
-                      "impl_flop_per_pair": FLOP_PER_PAIR[k]}
-        log("kernel %-15s %.3f ms  %.2f TFLOP/s (implementation count)" % (k, mean, kernels[k]["impl_tflops"]))
-    # the dominant unit of the method: the adjoint (both of its launches)
-    adj_ms = kernels["adjoint_source"]["mean_ms"] + kernels["adjoint_target"]["mean_ms"]
-    achieved = round(pairs * METHOD_FLOP["adjoint"] / (adj_ms * 1e-3) / 1e12, 3)
-    dom = max(("adjoint_source", "adjoint_target"), key=lambda k: kernels[k]["mean_ms"])
-    counters = measured_counters(dom, bs, args.n)
+    del Cs
+    if fs is None:
+        fs = sf  # forward schedule of the two-level step (W8 / W8P2 also serve the plain forward)
+    # roofline: the step's two launches together, at the method's 780 FLOP per
+    # pair (the forward's 224 and the adjoint's 556): the forward launch does
+    # part of the adjoint's work, so neither launch alone has a method count
+    step_kern_ms = kernels["forward_save"]["mean_ms"] + kernels["adjoint_saved"]["mean_ms"]
+    achieved = round(pairs * METHOD_FLOP["step"] / (step_kern_ms * 1e-3) / 1e12, 3)
+    dom = max(("forward_save", "adjoint_saved"), key=lambda k: kernels[k]["mean_ms"])
+    counters = measured_counters(dom, sf if dom == "forward_save" else sb, args.n)
     traffic = None if counters is None else counters["fetch_bytes"] + counters["write_bytes"]
     issued = None if counters is None else round(
         counters["issued_fp64_flop"] / (kernels[dom]["mean_ms"] * 1e-3) / 1e12, 3)
-    fwd_pairs_s = pairs / (kernels["forward"]["mean_ms"] * 1e-3)
-    fwd_tflops = pairs * METHOD_FLOP["forward"] / (kernels["forward"]["mean_ms"] * 1e-3) / 1e12
-    sum_ms = sum(v["mean_ms"] for v in kernels.values())
+    fwd_pairs_s = fwd_tflops = None
+    if "forward" in kernels:
+        fwd_pairs_s = pairs / (kernels["forward"]["mean_ms"] * 1e-3)
+        fwd_tflops = pairs * METHOD_FLOP["forward"] / (kernels["forward"]["mean_ms"] * 1e-3) / 1e12
+    sum_ms = step_kern_ms
     fwdbwd_flops = pairs * METHOD_FLOP["step"] / (ms_per_step * 1e-3) / 1e12
 
     # copy of known size, for scaling HBM counters (not part of the step)
@@ -264,28 +317,29 @@ def main():
                         % (args.n, 8 * args.n),
             "subgrids": batch["S"], "cells": batch["S"] * 512, "pairs": pairs,
             "field": batch["field"],
-            "schedules": {"forward": sched_name(fs), "adjoint_target": sched_name(bs & 0xff),
-                          "adjoint_source": sched_name(bs >> 8)},
+            "schedules": {"forward_save": sched_name(sf), "adjoint_saved": sched_name(sb)},
+            "step": "forward with saved target-side sums + one-pass adjoint (two launches)",
             "parallelism": "single GPU",
         },
         "roofline": {
-            "bound": "alu", "kernel": "adjoint (source-role + target-role launches)",
+            "bound": "alu", "kernel": "the step's two launches (forward with saved sums + one-pass adjoint)",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
             "traffic_kernel": dom,
-            "traffic_unit": "bytes per launch of the longer adjoint launch (HBM side, FETCH_SIZE + "
+            "traffic_unit": "bytes per launch of the longer of the two launches (HBM side, FETCH_SIZE + "
                             "WRITE_SIZE, copy-calibrated)",
-            "flop_basis": "method-level FP64 ops per cell pair of the adjoint, 556 (FMA = 2, rsqrt = 1) "
-                          "x exact pairs, over the summed mean durations of its launches",
+            "flop_basis": "method-level FP64 ops per cell pair of forward + adjoint, 780 (FMA = 2, rsqrt = 1) "
+                          "x exact pairs, over the summed mean durations of the two launches",
             "issued_fp64_tflops": issued,
-            "issued_basis": "FP64 operations per launch of the longer adjoint launch counted by rocprofv3 "
+            "issued_basis": "FP64 operations per launch of the longer launch counted by rocprofv3 "
                             "(64 x (2 FMA + MUL + ADD + TRANS) instruction counters, committed summary) "
                             "/ its live mean duration",
         },
         "kernels": kernels,
         "method_flop_per_pair": METHOD_FLOP,
-        "fwd_tflops": round(fwd_tflops, 3),
-        "fwd_frac_fp64_peak": round(fwd_tflops / PEAK_FP64_TFLOPS, 4),
+        "three_launch_step": two_pass,
+        "fwd_tflops": None if fwd_tflops is None else round(fwd_tflops, 3),
+        "fwd_frac_fp64_peak": None if fwd_tflops is None else round(fwd_tflops / PEAK_FP64_TFLOPS, 4),
         "fwd_bwd_tflops": round(fwdbwd_flops, 3),
         "fwd_bwd_frac_fp64_peak": round(fwdbwd_flops / PEAK_FP64_TFLOPS, 4),
         "fwd_pairs_per_s": fwd_pairs_s,

@@ -231,6 +231,46 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
                               const double* gL, double* gM, double* gcom, int sched,
                               void* stream);
 
+/* Training step in two passes instead of three: a forward that also saves
+ * what the adjoint's target role needs, and a one-pass adjoint.
+ *
+ * ot_fmm_multipole_batched_save: L as ot_fmm_multipole_batched, and
+ *   Cs[24][T*512], the target-side derivatives of L,
+ *     C'_g(i) = sum_{j in S(i)} sum_{|b| <= 4-|g|} s_b M_b(j) G_{g+b}(X_i - X_j),
+ *     1 <= |g| <= 4, so that dL_a(i)/dX_i,k (target role only) = C'_{a+e_k}(i);
+ *   the 24 components with a z exponent below 2, in graded-lex order (x, y, z,
+ *   xx, xy, xz, yy, yz, xxx, xxy, xxz, xyy, xyz, yyy, yyz, xxxx, xxxy, xxxz,
+ *   xxyy, xxyz, xyyy, xyyz, yyyy, yyyz); the other 10 follow from Laplace's
+ *   equation, C'_{g+zz} = -(C'_{g+xx} + C'_{g+yy}).
+ * ot_fmm_multipole_backward_saved: gM, gcom exactly as
+ *   ot_fmm_multipole_backward (overwritten), from gL and the Cs of the forward
+ *   of the same M and com: one pass over the store sub-grids (source role),
+ *   whose cells add their own target role from Cs.
+ * Schedules: W8 or W8P2 with the PERSISTENT / LOCAL flags, or AUTO (the
+ * choice of ot_fmm_autotune_saved, else W8P2 | PERSISTENT | LOCAL); 16
+ * wavefronts are EINVAL. Errors and overlap rules as for the other batched
+ * calls (Cs counts as an output of the forward and an input of the adjoint). */
+int ot_fmm_multipole_batched_save(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                  double* Cs, int sched, void* stream);
+int ot_fmm_multipole_backward_saved(ot_fmm_plan plan, const double* M, const double* com,
+                                    const double* gL, const double* Cs, double* gM, double* gcom,
+                                    int sched, void* stream);
+
+/* Times both passes of the two-pass step with every schedule (W8, W8P2, each
+ * with the four flag combinations) on the given buffers and keeps the fastest
+ * in the plan (used by AUTO); leaves the results of the chosen schedules in
+ * L, Cs, gM and gcom. Synchronizes `stream`; not while capturing. */
+int ot_fmm_autotune_saved(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                          double* Cs, const double* gL, double* gM, double* gcom, void* stream,
+                          int* fwd_sched, int* bwd_sched);
+
+/* Captures the two-pass step (forward with saved sums, one-pass adjoint)
+ * into the plan's step graph (replacing any previous one), replayed by
+ * ot_fmm_step_graph_launch. */
+int ot_fmm_step_graph_create_saved(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                   double* Cs, const double* gL, double* gM, double* gcom,
+                                   int fwd_sched, int bwd_sched);
+
 /* Times every schedule of the forward (and backward, if gL/gM/gcom are not
  * NULL) on the given buffers and stores the fastest in the plan; returns the
  * choices. Every shape is timed with each combination of the persistent and
@@ -255,10 +295,13 @@ int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream);
  * every forward / adjoint launch of the plan (not graph replays) is
  * bracketed by HIP events on its stream. ot_fmm_plan_kernel_times waits for
  * the recorded events, returns for each kernel -- [0] batched forward,
- * [1] adjoint source-role pass, [2] adjoint target-role pass -- the summed
- * duration in ms and the number of launches, and resets the counters. */
+ * [1] adjoint source-role pass, [2] adjoint target-role pass, [3] forward
+ * with saved sums, [4] one-pass adjoint -- the summed duration in ms and the
+ * number of launches, and resets the counters. */
+#define OT_FMM_NKERNELS 5
 int ot_fmm_plan_timing(ot_fmm_plan plan, int enable);
-int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launches[3]);
+int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[OT_FMM_NKERNELS],
+                             int64_t launches[OT_FMM_NKERNELS]);
 
 /* ---------------------------------------------------------------------------
  * Tree passes around the interaction (paper Sec. 2.1 and 2.3: the FMM gravity

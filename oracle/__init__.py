@@ -60,7 +60,7 @@ def _load():
     for f in (lib.orc_block_forward, lib.orc_block_forward_full):
         f.argtypes = [P, i, P, i, P, P, i]
         f.restype = i
-    for f in (lib.orc_batched_forward, lib.orc_batched_forward_full):
+    for f in (lib.orc_batched_forward, lib.orc_batched_forward_full, lib.orc_batched_forward_tgrad):
         f.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
         f.restype = i
     for f in (lib.orc_batched_forward_cs, lib.orc_batched_forward_cs_full,
@@ -171,6 +171,24 @@ def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: in
     if rc:
         raise ValueError("orc_batched_forward rejected its arguments")
     return (L, A) if want_abs else L
+
+
+def batched_forward_tgrad(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0):
+    """Target-side derivatives of the forward, D[a, k] = dL_a(i)/dX_i,k with the
+    sources' centres held fixed, over a selection of targets.
+    Returns D (20, 3, nsel*512) (and A, the term magnitudes, if want_abs)."""
+    S, T, tgt, nbr, shift, period = _batch_args(batch)
+    tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
+    M = _f64(M)
+    X = _f64(X)
+    assert M.shape == (NM, S * SUB3) and X.shape == (3, S * SUB3)
+    D = np.zeros((NM, 3, len(tsel) * SUB3), np.float64)
+    A = np.zeros_like(D) if want_abs else None
+    rc = _load().orc_batched_forward_tgrad(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M),
+                                           _ptr(X), _ptr(tsel), len(tsel), _ptr(D), _ptr(A), nthreads)
+    if rc:
+        raise ValueError("orc_batched_forward_tgrad rejected its arguments")
+    return (D, A) if want_abs else D
 
 
 def batched_forward_cs(batch, M, Xre, Xim, tsel=None, nthreads: int = 0, full: bool = False):

@@ -471,6 +471,79 @@ int orc_batched_forward_full(int S, int T, const int32_t *tgt, const int32_t *nb
     return batched_forward(1, S, T, tgt, nbr, shift, period, M, X, tsel, nsel, L, Aabs, nthreads);
 }
 
+/* Target-side derivatives of the forward: the chain rule applied to the
+ * definition of L_alpha(i) with respect to the target's own centre X_i only
+ * (the sources' centres held fixed); d/dX_i,k of G_{alpha+beta}(X_i - X_j) is
+ * G_{alpha+beta+e_k}(X_i - X_j), so
+ *   D_{alpha,k}(i) = sum_{j in S(i)} sum_{|beta| <= 3-|alpha|}
+ *                        s_beta M_beta(j) G_{alpha+beta+e_k}(X_i - X_j).
+ * (Cell i is never one of its own sources, so this is the whole derivative of
+ * L(i) with respect to X_i whenever i's sub-grid appears only in slot 13.)
+ * Output D[20][3][nsel*512] for targets tsel; Aabs (may be NULL): the sums of
+ * the magnitudes of the terms. */
+static void pair_tgrad(const double Xi[3], const double Xj[3], const double *Mj, double *D, double *Aabs)
+{
+    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
+    double G[NG];
+    green_re(r, 4, G);
+    for (int a = 0; a < NM; ++a)
+        for (int k = 0; k < 3; ++k)
+            for (int b = 0; b < NM; ++b) {
+                if (order_of(a) + order_of(b) > 3) continue;
+                double term = taylor_sign(b) * Mj[b] * G[sum_index(sum_index(a, b), 1 + k)];
+                D[a * 3 + k] += term;
+                if (Aabs) Aabs[a * 3 + k] += fabs(term);
+            }
+}
+
+int orc_batched_forward_tgrad(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
+                              const double *period, const double *M, const double *X, const int32_t *tsel,
+                              int nsel, double *D, double *Aabs, int nthreads)
+{
+    init_tables();
+    if (check_batch(S, T, tgt, nbr)) return -1;
+    for (int q = 0; q < nsel; ++q)
+        if (tsel[q] < 0 || tsel[q] >= T) return -1;
+    const size_t NS = (size_t)S * SUB3;
+    const size_t NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int q = 0; q < nsel; ++q)
+        for (int ci = 0; ci < SUB3; ++ci) {
+            int t = tsel[q];
+            int li[3];
+            local_coords(ci, li);
+            int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+            size_t iidx = (size_t)tgt[t] * SUB3 + ci;
+            double Xi[3] = {X[iidx], X[NS + iidx], X[2 * NS + iidx]};
+            double acc[NM * 3] = {0}, aabs[NM * 3] = {0};
+            for (int slot = 0; slot < 27; ++slot) {
+                int blk = nbr[t * 27 + slot];
+                if (blk < 0) continue;
+                int so[3];
+                slot_coords(slot, so);
+                double sh[3];
+                neighbour_shift(shift, period, t, slot, sh);
+                for (int cj = 0; cj < SUB3; ++cj) {
+                    int lj[3];
+                    local_coords(cj, lj);
+                    int hj[3] = {8 * so[0] + lj[0], 8 * so[1] + lj[1], 8 * so[2] + lj[2]};
+                    if (!in_stencil(hi, hj)) continue;
+                    size_t jidx = (size_t)blk * SUB3 + cj;
+                    double Xj[3] = {X[jidx] + sh[0], X[NS + jidx] + sh[1], X[2 * NS + jidx] + sh[2]};
+                    double Mj[NM];
+                    for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
+                    pair_tgrad(Xi, Xj, Mj, acc, Aabs ? aabs : NULL);
+                }
+            }
+            for (int a = 0; a < NM * 3; ++a) {
+                D[a * NO + (size_t)q * SUB3 + ci] = acc[a];
+                if (Aabs) Aabs[a * NO + (size_t)q * SUB3 + ci] = aabs[a];
+            }
+        }
+    return 0;
+}
+
 /* Coarse substitute for missing neighbours -- a reading: the paper gives no
  * FMM formulas; at a refinement boundary an FMM lets fine cells interact with
  * the coarser cells that cover a region holding no fine cells.

@@ -91,6 +91,15 @@ _lib.ot_fmm_plan_timing.argtypes = [_P, _I]
 _lib.ot_fmm_plan_timing.restype = _I
 _lib.ot_fmm_plan_kernel_times.argtypes = [_P, _P, _P]
 _lib.ot_fmm_plan_kernel_times.restype = _I
+_lib.ot_fmm_multipole_batched_save.argtypes = [_P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_batched_save.restype = _I
+_lib.ot_fmm_multipole_backward_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_backward_saved.restype = _I
+_lib.ot_fmm_autotune_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                       ctypes.POINTER(_I), ctypes.POINTER(_I)]
+_lib.ot_fmm_autotune_saved.restype = _I
+_lib.ot_fmm_step_graph_create_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _I, _I]
+_lib.ot_fmm_step_graph_create_saved.restype = _I
 _lib.ot_fmm_multipole_batched_noalloc.argtypes = [_I32, _I32, _P, _P, _P, _P, _P, _P, _P, _P]
 _lib.ot_fmm_multipole_batched_noalloc.restype = _I
 _lib.ot_fmm_noalloc_status.argtypes = [ctypes.POINTER(_I32), ctypes.POINTER(_I32)]
@@ -134,7 +143,8 @@ for _n in ("executor_create", "executor_destroy", "executor_stream", "executor_g
            "future_release"):
     getattr(_lib, "ot_fmm_" + _n).restype = _I
 
-KERNELS = ("forward", "adjoint_source", "adjoint_target")
+KERNELS = ("forward", "adjoint_source", "adjoint_target", "forward_save", "adjoint_saved")
+NSAVED = 24  # saved target-side sums per target cell (ot_fmm_multipole_batched_save)
 
 
 class OtFmmError(RuntimeError):
@@ -325,6 +335,43 @@ class Plan:
             "ot_fmm_multipole_backward_full")
         return gM, gcom
 
+    def multipole_batched_save(self, M, com, L, Cs, sched=SCHED_AUTO, stream=None):
+        """Forward that also writes the target-side derivative sums Cs
+        (24, T*512) the one-pass adjoint needs."""
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_batched_save(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+            _dptr(Cs, (NSAVED, sl[1]), "Cs"), int(sched), _stream(stream)), "ot_fmm_multipole_batched_save")
+        return L, Cs
+
+    def multipole_backward_saved(self, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None):
+        """One-pass adjoint from the sums of multipole_batched_save (gM, gcom overwritten)."""
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_backward_saved(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(gL, sl, "gL"),
+            _dptr(Cs, (NSAVED, sl[1]), "Cs"), _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"), int(sched),
+            _stream(stream)), "ot_fmm_multipole_backward_saved")
+        return gM, gcom
+
+    def autotune_saved(self, M, com, L, Cs, gL, gM, gcom, stream=None):
+        sm, sx, sl = self._shapes()
+        f = ctypes.c_int()
+        b = ctypes.c_int()
+        _check(_lib.ot_fmm_autotune_saved(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+            _dptr(Cs, (NSAVED, sl[1]), "Cs"), _dptr(gL, sl, "gL"), _dptr(gM, sm, "gM"),
+            _dptr(gcom, sx, "gcom"), _stream(stream), ctypes.byref(f), ctypes.byref(b)),
+            "ot_fmm_autotune_saved")
+        return f.value, b.value
+
+    def step_graph_create_saved(self, M, com, L, Cs, gL, gM, gcom, fwd_sched=SCHED_AUTO,
+                                bwd_sched=SCHED_AUTO):
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_step_graph_create_saved(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+            _dptr(Cs, (NSAVED, sl[1]), "Cs"), _dptr(gL, sl, "gL"), _dptr(gM, sm, "gM"),
+            _dptr(gcom, sx, "gcom"), int(fwd_sched), int(bwd_sched)), "ot_fmm_step_graph_create_saved")
+
     def autotune(self, M, com, L, gL=None, gM=None, gcom=None, stream=None):
         sm, sx, sl = self._shapes()
         f = ctypes.c_int()
@@ -348,8 +395,8 @@ class Plan:
 
     def kernel_times(self):
         """{kernel: (total ms, launches)} since the last call (waits for the events)."""
-        ms = np.zeros(3, np.float64)
-        n = np.zeros(3, np.int64)
+        ms = np.zeros(len(KERNELS), np.float64)
+        n = np.zeros(len(KERNELS), np.int64)
         _check(_lib.ot_fmm_plan_kernel_times(self.handle, ms.ctypes.data_as(_P),
                                              n.ctypes.data_as(_P)), "ot_fmm_plan_kernel_times")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
@@ -373,6 +420,14 @@ def ot_fmm_multipole_batched_full(plan, M, com, L, sched=SCHED_AUTO, stream=None
 
 def ot_fmm_multipole_backward_full(plan, M, com, gL, gM, gcom, sched=SCHED_AUTO, stream=None):
     return plan.multipole_backward_full(M, com, gL, gM, gcom, sched, stream)
+
+
+def ot_fmm_multipole_batched_save(plan, M, com, L, Cs, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_batched_save(M, com, L, Cs, sched, stream)
+
+
+def ot_fmm_multipole_backward_saved(plan, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom, sched, stream)
 
 
 def ot_fmm_plan_set_coarse(plan, Sp, coarse, octant):
@@ -435,38 +490,56 @@ class MultipoleBatched(torch.autograd.Function):
     """L = multipole_batched(M, com) with the hand-written adjoint as backward
     (full=True: the full truncation and its adjoint).
 
-    Usage: L = MultipoleBatched.apply(M, com, plan[, full])."""
+    With the total-order truncation and a gradient to compute, the forward
+    also keeps the target-side sums (24 doubles per target cell) and the
+    backward is the one-pass adjoint (save=False: plain forward, two-pass
+    adjoint).
+
+    Usage: L = MultipoleBatched.apply(M, com, plan[, full[, save]])."""
 
     @staticmethod
-    def forward(ctx, M, com, plan, full=False):
+    def forward(ctx, M, com, plan, full=False, save=True):
         M = M.contiguous()
         com = com.contiguous()
         L = torch.empty((20, plan.T * 512), dtype=torch.float64, device=M.device)
+        use_save = bool(save) and not full and any(ctx.needs_input_grad[:2])
         if full:
             plan.multipole_batched_full(M, com, L)
+            ctx.save_for_backward(M, com)
+        elif use_save:
+            Cs = torch.empty((NSAVED, plan.T * 512), dtype=torch.float64, device=M.device)
+            plan.multipole_batched_save(M, com, L, Cs)
+            ctx.save_for_backward(M, com, Cs)
         else:
             plan.multipole_batched(M, com, L)
-        ctx.save_for_backward(M, com)
+            ctx.save_for_backward(M, com)
         ctx.plan = plan
         ctx.full = bool(full)
+        ctx.use_save = use_save
         return L
 
     @staticmethod
     def backward(ctx, gL):
-        M, com = ctx.saved_tensors
         gL = gL.contiguous()
-        gM = torch.empty_like(M)
-        gcom = torch.empty_like(com)
-        if ctx.full:
-            ctx.plan.multipole_backward_full(M, com, gL, gM, gcom)
+        if ctx.use_save:
+            M, com, Cs = ctx.saved_tensors
+            gM = torch.empty_like(M)
+            gcom = torch.empty_like(com)
+            ctx.plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom)
         else:
-            ctx.plan.multipole_backward(M, com, gL, gM, gcom)
-        return gM, gcom, None, None
+            M, com = ctx.saved_tensors
+            gM = torch.empty_like(M)
+            gcom = torch.empty_like(com)
+            if ctx.full:
+                ctx.plan.multipole_backward_full(M, com, gL, gM, gcom)
+            else:
+                ctx.plan.multipole_backward(M, com, gL, gM, gcom)
+        return gM, gcom, None, None, None
 
 
-def multipole(M, com, plan, full=False):
+def multipole(M, com, plan, full=False, save=True):
     """Differentiable batched multipole interaction (see MultipoleBatched)."""
-    return MultipoleBatched.apply(M, com, plan, full)
+    return MultipoleBatched.apply(M, com, plan, full, save)
 
 
 # ---------------------------------------------------------------------------

@@ -156,6 +156,14 @@ constexpr int kCounterSlots = kEagerSlots + kCaptureSlots;
 // 6% faster than one pass of 8 wavefronts for the forward and the adjoint
 constexpr int kFullSched = OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL;
 
+// default schedule of the forward with saved sums and of the one-pass adjoint
+// when the plan has not been tuned (their 40 accumulators rule out 16
+// wavefronts, as for the two-pass adjoint's source role)
+constexpr int kSaveSched = OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL;
+
+// kernels timed by the plan's events (ot_fmm_plan_kernel_times)
+constexpr int kTimedKernels = 5;
+
 int pick_fwd(int sched, int tuned)
 {
     if (sched == OT_FMM_SCHED_AUTO) sched = tuned ? tuned : OT_FMM_SCHED_W16;
@@ -173,6 +181,7 @@ struct ot_fmm_plan_s {
     int4* d_fwd_rel = nullptr;  // [T][27]
     int4* d_rev_rel = nullptr;  // [S][27]
     int* d_tgt = nullptr;       // [T]
+    int* d_store_tgt = nullptr; // [S] target index of each store sub-grid, -1 if none
     int* d_fwd_order = nullptr; // [T] longest work first
     int* d_rev_order = nullptr; // [S]
     int* d_fwd_local = nullptr; // [T] XCD-aware (OT_FMM_SCHED_LOCAL)
@@ -186,6 +195,7 @@ struct ot_fmm_plan_s {
     int fwd_piece_off[kMaxPieces + 1] = {0};
     int rev_piece_off[kMaxPieces + 1] = {0};
     int tuned_fwd = 0, tuned_bwd = 0;
+    int tuned_save = 0, tuned_saved_bwd = 0;  // forward with saved sums, one-pass adjoint
     // persistent launches: kMaxPieces work counters per slot; slots
     // [0, kEagerSlots) belong to streams (eager launches), the others to
     // launches recorded into graphs (see counter_slot)
@@ -200,10 +210,11 @@ struct ot_fmm_plan_s {
     int n_cu = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    // per-kernel timing (forward, adjoint source pass, adjoint target pass)
+    // per-kernel timing (forward, adjoint source pass, adjoint target pass,
+    // forward with saved sums, one-pass adjoint)
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[3];
-    size_t ev_used[3] = {0, 0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kTimedKernels];
+    size_t ev_used[kTimedKernels] = {0, 0, 0, 0, 0};
     // coarse substitutes for missing neighbours (ot_fmm_plan_set_coarse)
     std::vector<uint32_t> missing;  // [T] bit s: slot s has no fine neighbour
     int32_t Sp_coarse = 0;
@@ -476,6 +487,78 @@ int bwd_batched(ot_fmm_plan plan, const double* M, const double* com, const doub
     return bwd_any<false>(plan, M, com, gL, gM, gcom, sched, stream);
 }
 
+// A schedule of the forward with saved sums or of the one-pass adjoint:
+// AUTO, or W8 / W8P2 with the persistent and XCD-aware flags.
+bool valid_save_sched(int s)
+{
+    return s == OT_FMM_SCHED_AUTO || (valid_fwd_sched(s) && (s & kShapeMask) != OT_FMM_SCHED_W16);
+}
+
+// Forward that also writes the target-role sums of the adjoint,
+// C'_g(i) = sum_j sum_{|b| <= 4-|g|} s_b M_b(j) G_{g+b}(X_i - X_j), 1 <= |g| <= 4
+// (= dL_a(i)/dX_i,k for g = a + e_k), 24 kept components [24][T*512].
+int fwd_save_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, double* Cs, int sched,
+                     hipStream_t stream)
+{
+    KParams kp{};
+    kp.mom = M;
+    kp.pos = com;
+    kp.mom_stride = (long)plan->S * kSub3;
+    kp.pos_stride = (long)plan->S * kSub3;
+    kp.rel = plan->d_fwd_rel;
+    kp.own_blk = plan->d_tgt;
+    kp.order = plan->d_fwd_order;
+    kp.out0 = L;
+    kp.out1 = Cs;
+    kp.out_stride = (long)plan->T * kSub3;
+    kp.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
+    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_save ? plan->tuned_save : kSaveSched;
+    const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
+    apply_order(kp, plan, sched, false);
+    const int shape = sched & kShapeMask;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FS_STORE, 8>(plan, 3, kp, plan->T, pers, stream);
+    if (shape == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_FS_STORE, 8, 2>(plan, 3, kp, plan->T, pers, stream);
+    return fail(OT_FMM_EINVAL, "unknown schedule for the forward with saved sums");
+}
+
+// One-pass adjoint from the saved sums: the source-role pass over every store
+// sub-grid, whose epilogue adds the target role of the sub-grid's own cells
+// (when it is a target) from the saved sums and gL.
+int bwd_saved_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL, const double* Cs,
+                      double* gM, double* gcom, int sched, hipStream_t stream)
+{
+    const long NS = (long)plan->S * kSub3, NT = (long)plan->T * kSub3;
+    KParams kp{};
+    kp.mom = gL;
+    kp.mom_stride = NT;
+    kp.pos = com;
+    kp.pos_stride = NS;
+    kp.rel = plan->d_rev_rel;
+    kp.own_blk = nullptr;
+    kp.order = plan->d_rev_order;
+    kp.aux = M;
+    kp.aux_stride = NS;
+    kp.store_tgt = plan->d_store_tgt;
+    kp.aux2 = gL;
+    kp.save = Cs;
+    kp.aux_stride2 = NT;
+    kp.out0 = gM;
+    kp.out1 = gcom;
+    kp.out_stride = NS;
+    kp.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
+    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_saved_bwd ? plan->tuned_saved_bwd : kSaveSched;
+    const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
+    apply_order(kp, plan, sched, true);
+    const int shape = sched & kShapeMask;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_B2S_STORE, 8>(plan, 4, kp, plan->S, pers, stream);
+    if (shape == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_B2S_STORE, 8, 2>(plan, 4, kp, plan->S, pers, stream);
+    return fail(OT_FMM_EINVAL, "unknown schedule for the one-pass adjoint");
+}
+
 int check_plan(ot_fmm_plan plan)
 {
     if (!plan) return fail(OT_FMM_EINVAL, "null plan");
@@ -500,6 +583,7 @@ void free_plan_memory(ot_fmm_plan p)
     (void)hipFree(p->d_fwd_rel);
     (void)hipFree(p->d_rev_rel);
     (void)hipFree(p->d_tgt);
+    (void)hipFree(p->d_store_tgt);
     (void)hipFree(p->d_fwd_order);
     (void)hipFree(p->d_rev_order);
     (void)hipFree(p->d_fwd_local);
@@ -728,6 +812,81 @@ int build_host_tables(int32_t S, int32_t T, const int32_t* tgt, const int32_t* n
 
 }  // namespace
 
+namespace {
+// Captures the launches `enqueue(stream)` makes into the plan's step graph
+// (replacing any previous one): the counter slots its persistent launches
+// take belong to the graph and return to the pool when it is replaced.
+template <class F>
+int capture_step_graph(ot_fmm_plan plan, F&& enqueue)
+{
+    hipStream_t cs;
+    OT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    const bool timing = plan->timing;
+    plan->timing = false;  // no timing events inside the graph
+    std::vector<int> slots;  // counter slots the captured launches take
+    {
+        std::lock_guard<std::mutex> lock(plan->slot_mutex);
+        plan->capture_log = &slots;
+        plan->capture_stream = cs;
+    }
+    int rc = enqueue(cs);
+    plan->timing = timing;
+    {
+        std::lock_guard<std::mutex> lock(plan->slot_mutex);
+        plan->capture_log = nullptr;
+        plan->capture_stream = nullptr;
+    }
+    // slots of a graph that is never instantiated go back to the pool
+    auto give_back = [&](const std::vector<int>& v) {
+        std::lock_guard<std::mutex> lock(plan->slot_mutex);
+        plan->free_capture.insert(plan->free_capture.end(), v.begin(), v.end());
+    };
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        give_back(slots);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        give_back(slots);
+        return hip_fail(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        give_back(slots);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    if (plan->graph_exec) {
+        // a replay of the graph being replaced may still run: its counter
+        // slots are reused only once the device is idle
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            (void)hipGraphDestroy(g);
+            give_back(slots);
+            return hip_fail(e, "hipDeviceSynchronize");
+        }
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        give_back(plan->graph_slots);
+    }
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    plan->graph = g;
+    plan->graph_exec = ex;
+    plan->graph_slots.swap(slots);
+    return OT_FMM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ot_fmm_version(void) { return OT_FMM_VERSION; }
@@ -829,9 +988,12 @@ int ot_fmm_plan_create(int32_t S, int32_t T, const int32_t* tgt, const int32_t* 
         p->fwd_piece_off[k] = ht.fo_off[k];
         p->rev_piece_off[k] = ht.ro_off[k];
     }
+    std::vector<int> store_tgt(S, -1);
+    for (int t = 0; t < T; ++t) store_tgt[tg[t]] = t;
     const std::vector<int> zeros((size_t)kCounterSlots * kMaxPieces, 0);
     if ((rc = upload(&p->d_fwd_rel, fwd)) || (rc = upload(&p->d_rev_rel, rev)) ||
-        (rc = upload(&p->d_tgt, tg)) || (rc = upload(&p->d_fwd_order, fo)) ||
+        (rc = upload(&p->d_tgt, tg)) || (rc = upload(&p->d_store_tgt, store_tgt)) ||
+        (rc = upload(&p->d_fwd_order, fo)) ||
         (rc = upload(&p->d_rev_order, ro)) || (rc = upload(&p->d_counters, zeros)) ||
         (rc = upload(&p->d_fwd_local, ht.fo_local)) || (rc = upload(&p->d_rev_local, ht.ro_local)) ||
         (rc = upload(&p->d_fwd_piece, ht.fo_piece)) || (rc = upload(&p->d_rev_piece, ht.ro_piece))) {
@@ -1180,6 +1342,152 @@ int ot_fmm_multipole_backward_full(ot_fmm_plan plan, const double* M, const doub
     return bwd_any<true>(plan, M, com, gL, gM, gcom, sched, (hipStream_t)stream);
 }
 
+int ot_fmm_multipole_batched_save(ot_fmm_plan plan, const double* M, const double* com, double* L, double* Cs,
+                                  int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L) || !aligned16(Cs))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    if (overlap(Cs, 24 * NT, M, 20 * NS) || overlap(Cs, 24 * NT, com, 3 * NS) || overlap(Cs, 24 * NT, L, 20 * NT))
+        return fail(OT_FMM_EINVAL, "the saved sums overlap an input or L");
+    if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
+    return fwd_save_batched(plan, M, com, L, Cs, sched, (hipStream_t)stream);
+}
+
+// Extents rule of the one-pass adjoint: gM and gcom overlap no input and not
+// each other.
+static int check_saved_bwd(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
+                           const double* Cs, const double* gM, const double* gcom)
+{
+    if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(Cs) || !aligned16(gM) ||
+        !aligned16(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    const double* in[4] = {M, com, gL, Cs};
+    const int64_t nin[4] = {20 * NS, 3 * NS, 20 * NT, 24 * NT};
+    for (int i = 0; i < 4; ++i)
+        if (overlap(gM, 20 * NS, in[i], nin[i]) || overlap(gcom, 3 * NS, in[i], nin[i]))
+            return fail(OT_FMM_EINVAL, "outputs overlap inputs");
+    if (overlap(gM, 20 * NS, gcom, 3 * NS)) return fail(OT_FMM_EINVAL, "gM overlaps gcom");
+    return OT_FMM_OK;
+}
+
+// Extents rule of a whole step with saved sums: the adjoint's rule, and L
+// and the sums overlap no other array.
+static int check_saved_step(ot_fmm_plan plan, const double* M, const double* com, const double* L,
+                            const double* Cs, const double* gL, const double* gM, const double* gcom)
+{
+    if (!aligned16(L)) return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    int rc = check_saved_bwd(plan, M, com, gL, Cs, gM, gcom);
+    if (rc) return rc;
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS) || overlap(Cs, 24 * NT, M, 20 * NS) ||
+        overlap(Cs, 24 * NT, com, 3 * NS) || overlap(Cs, 24 * NT, L, 20 * NT) || overlap(L, 20 * NT, gL, 20 * NT) ||
+        overlap(Cs, 24 * NT, gL, 20 * NT) || overlap(gM, 20 * NS, L, 20 * NT) || overlap(gcom, 3 * NS, L, 20 * NT))
+        return fail(OT_FMM_EINVAL, "arrays overlap");
+    return OT_FMM_OK;
+}
+
+int ot_fmm_multipole_backward_saved(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
+                                    const double* Cs, double* gM, double* gcom, int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if ((rc = check_saved_bwd(plan, M, com, gL, Cs, gM, gcom))) return rc;
+    if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
+    return bwd_saved_batched(plan, M, com, gL, Cs, gM, gcom, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_autotune_saved(ot_fmm_plan plan, const double* M, const double* com, double* L, double* Cs,
+                          const double* gL, double* gM, double* gcom, void* stream, int* fwd_sched,
+                          int* bwd_sched)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if ((rc = check_saved_step(plan, M, com, L, Cs, gL, gM, gcom))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    struct Events {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~Events()
+        {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    OT_HIP(hipEventCreate(&ev.a));
+    OT_HIP(hipEventCreate(&ev.b));
+    auto time_it = [&](auto&& fn, float* ms) -> int {
+        int r = fn();  // warm-up
+        if (r) return r;
+        OT_HIP(hipEventRecord(ev.a, s));
+        for (int i = 0; i < 3; ++i)
+            if ((r = fn())) return r;
+        OT_HIP(hipEventRecord(ev.b, s));
+        OT_HIP(hipEventSynchronize(ev.b));
+        OT_HIP(hipEventElapsedTime(ms, ev.a, ev.b));
+        return OT_FMM_OK;
+    };
+    const int kFlags[4] = {0, OT_FMM_SCHED_PERSISTENT, OT_FMM_SCHED_LOCAL,
+                           OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL};
+    int best_f = kSaveSched, best_b = kSaveSched;
+    float best_fms = 3.0e38f, best_bms = 3.0e38f;
+    for (int shape : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
+        for (int f : kFlags) {
+            const int cand = shape | f;
+            float ms = 0.0f;
+            if (!rc) rc = time_it([&] { return fwd_save_batched(plan, M, com, L, Cs, cand, s); }, &ms);
+            if (!rc && ms < best_fms) {
+                best_fms = ms;
+                best_f = cand;
+            }
+        }
+    // the adjoint is timed on the sums of the last forward (any schedule's
+    // sums are valid)
+    for (int shape : {OT_FMM_SCHED_W8, OT_FMM_SCHED_W8P2})
+        for (int f : kFlags) {
+            const int cand = shape | f;
+            float ms = 0.0f;
+            if (!rc) rc = time_it([&] { return bwd_saved_batched(plan, M, com, gL, Cs, gM, gcom, cand, s); }, &ms);
+            if (!rc && ms < best_bms) {
+                best_bms = ms;
+                best_b = cand;
+            }
+        }
+    // leave the results of the chosen schedules in the buffers
+    if (!rc) rc = fwd_save_batched(plan, M, com, L, Cs, best_f, s);
+    if (!rc) rc = bwd_saved_batched(plan, M, com, gL, Cs, gM, gcom, best_b, s);
+    if (!rc) OT_HIP(hipStreamSynchronize(s));
+    if (rc) return rc;
+    plan->tuned_save = best_f;
+    plan->tuned_saved_bwd = best_b;
+    if (fwd_sched) *fwd_sched = best_f;
+    if (bwd_sched) *bwd_sched = best_b;
+    return OT_FMM_OK;
+}
+
+int ot_fmm_step_graph_create_saved(ot_fmm_plan plan, const double* M, const double* com, double* L, double* Cs,
+                                   const double* gL, double* gM, double* gcom, int fwd_sched, int bwd_sched)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if ((rc = check_saved_step(plan, M, com, L, Cs, gL, gM, gcom))) return rc;
+    if (!valid_save_sched(fwd_sched) || !valid_save_sched(bwd_sched))
+        return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
+    return capture_step_graph(plan, [&](hipStream_t cs) {
+        int r = fwd_save_batched(plan, M, com, L, Cs, fwd_sched, cs);
+        if (!r) r = bwd_saved_batched(plan, M, com, gL, Cs, gM, gcom, bwd_sched, cs);
+        return r;
+    });
+}
+
 int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double* L,
                     const double* gL, double* gM, double* gcom, void* stream, int* fwd_sched,
                     int* bwd_sched)
@@ -1287,71 +1595,11 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     if (with_bwd && !valid_bwd_sched(bwd_sched))
         return fail(OT_FMM_EINVAL, "unknown backward schedule");
     if ((rc = check_overlaps(plan, M, com, L, gL, with_bwd ? gM : nullptr, gcom))) return rc;
-    hipStream_t cs;
-    OT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) {
-        (void)hipStreamDestroy(cs);
-        return hip_fail(e, "hipStreamBeginCapture");
-    }
-    const bool timing = plan->timing;
-    plan->timing = false;  // no timing events inside the graph
-    std::vector<int> slots;  // counter slots the captured launches take
-    {
-        std::lock_guard<std::mutex> lock(plan->slot_mutex);
-        plan->capture_log = &slots;
-        plan->capture_stream = cs;
-    }
-    rc = fwd_batched(plan, M, com, L, fwd_sched, cs);
-    if (!rc && with_bwd) rc = bwd_batched(plan, M, com, gL, gM, gcom, bwd_sched, cs);
-    plan->timing = timing;
-    {
-        std::lock_guard<std::mutex> lock(plan->slot_mutex);
-        plan->capture_log = nullptr;
-        plan->capture_stream = nullptr;
-    }
-    // slots of a graph that is never instantiated go back to the pool
-    auto give_back = [&](const std::vector<int>& v) {
-        std::lock_guard<std::mutex> lock(plan->slot_mutex);
-        plan->free_capture.insert(plan->free_capture.end(), v.begin(), v.end());
-    };
-    e = hipStreamEndCapture(cs, &g);
-    (void)hipStreamDestroy(cs);
-    if (rc) {
-        if (g) (void)hipGraphDestroy(g);
-        give_back(slots);
-        return rc;
-    }
-    if (e != hipSuccess) {
-        give_back(slots);
-        return hip_fail(e, "hipStreamEndCapture");
-    }
-    hipGraphExec_t ex = nullptr;
-    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        give_back(slots);
-        return hip_fail(e, "hipGraphInstantiate");
-    }
-    if (plan->graph_exec) {
-        // a replay of the graph being replaced may still run: its counter
-        // slots are reused only once the device is idle
-        e = hipDeviceSynchronize();
-        if (e != hipSuccess) {
-            (void)hipGraphExecDestroy(ex);
-            (void)hipGraphDestroy(g);
-            give_back(slots);
-            return hip_fail(e, "hipDeviceSynchronize");
-        }
-        (void)hipGraphExecDestroy(plan->graph_exec);
-        give_back(plan->graph_slots);
-    }
-    if (plan->graph) (void)hipGraphDestroy(plan->graph);
-    plan->graph = g;
-    plan->graph_exec = ex;
-    plan->graph_slots.swap(slots);
-    return OT_FMM_OK;
+    return capture_step_graph(plan, [&](hipStream_t cs) {
+        int r = fwd_batched(plan, M, com, L, fwd_sched, cs);
+        if (!r && with_bwd) r = bwd_batched(plan, M, com, gL, gM, gcom, bwd_sched, cs);
+        return r;
+    });
 }
 
 int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream)
@@ -1373,13 +1621,13 @@ int ot_fmm_plan_timing(ot_fmm_plan plan, int enable)
     return OT_FMM_OK;
 }
 
-int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[3], int64_t launches[3])
+int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[OT_FMM_NKERNELS], int64_t launches[OT_FMM_NKERNELS])
 {
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
     if (!ms_total || !launches) return fail(OT_FMM_EINVAL, "null output");
-    for (int w = 0; w < 3; ++w) {
+    for (int w = 0; w < kTimedKernels; ++w) {
         double tot = 0.0;
         for (size_t i = 0; i < plan->ev_used[w]; ++i) {
             const auto& ev = plan->ev_pool[w][i];

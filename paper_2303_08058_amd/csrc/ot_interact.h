@@ -478,7 +478,10 @@ enum Mode : int {
     MODE_B1_STORE = 4,   // adjoint, target role per target -> gX (accumulate)
     MODE_FULL_STORE = 5,  // batched forward, full truncation -> L
     MODE_B2F_STORE = 6,   // adjoint of the full truncation, source role -> gM, gX (overwrite)
-    MODE_B1F_STORE = 7    // adjoint of the full truncation, target role -> gX (accumulate)
+    MODE_B1F_STORE = 7,   // adjoint of the full truncation, target role -> gX (accumulate)
+    MODE_FS_STORE = 8,    // batched forward -> L, plus the target-role sums the adjoint needs
+    MODE_B2S_STORE = 9    // adjoint from those sums: source role per store sub-grid, plus the
+                          // target role of its cells from the saved sums -> gM, gX (overwrite)
 };
 
 constexpr int kMaxPieces = 16;  // work-list pieces (one per XCD) of a persistent launch
@@ -493,8 +496,15 @@ struct KParams {
     const int* order;      // work-group -> owner (NULL: identity)
     const double* aux;     // epilogue input: gL (B1) or M (B2), [20][aux_stride]
     long aux_stride;
+    // B2S epilogue, the target role of the owner's cells: store sub-grid ->
+    // target index (-1: none), that target's gL [20][aux_stride2] and its
+    // saved sums [24][aux_stride2]
+    const int* store_tgt;
+    const double* aux2;
+    const double* save;
+    long aux_stride2;
     double* out0;          // L, or gM (B2), or gX (B1)
-    double* out1;          // gX (B2)
+    double* out1;          // gX (B2), or the saved target-role sums (FS)
     long out_stride;
     const int* out_blk;    // owner -> output block (NULL: identity)
     double period[3];
@@ -513,15 +523,18 @@ struct ModeTraits {
     // staged source components: the mass, or the 16 trace-reduced moments
     static constexpr int nq = (MODE == MODE_MONO_HALO) ? 1 : kNRed;
     static constexpr int nc = nq + 3;  // + centre of mass
-    static constexpr bool adjoint =
-        (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE || MODE == MODE_B1F_STORE || MODE == MODE_B2F_STORE);
-    static constexpr bool source_role = (MODE == MODE_B2_STORE || MODE == MODE_B2F_STORE);
+    static constexpr bool adjoint = (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE ||
+                                     MODE == MODE_B1F_STORE || MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE);
+    static constexpr bool source_role = (MODE == MODE_B2_STORE || MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE);
+    // the F + E sums (total order 3, and the order-4 terms of orders 1..4)
+    static constexpr bool fe = (MODE == MODE_B2_STORE || MODE == MODE_B2S_STORE || MODE == MODE_FS_STORE);
     // accumulators: monopole 20; forward 16 kept of 20; target-role adjoint
-    // 24 kept of the 34 orders 1..4; source-role adjoint 16 + 24; with the
-    // full truncation the source role keeps one set for orders 0..4 (25)
+    // 24 kept of the 34 orders 1..4; source-role adjoint and the forward
+    // with saved sums 16 + 24; with the full truncation the source role keeps
+    // one set for orders 0..4 (25)
     static constexpr int nacc = (MODE == MODE_MONO_HALO)                             ? 20
                                 : (MODE == MODE_B1_STORE || MODE == MODE_B1F_STORE) ? 24
-                                : (MODE == MODE_B2_STORE)                           ? 40
+                                : fe                                                ? 40
                                 : (MODE == MODE_B2F_STORE)                          ? 25
                                                                                     : 16;
 };
@@ -793,7 +806,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
                         radial<7>(rx, ry, rz, D);
                         const double rr[3] = {rx, ry, rz};
                         contract_full<0>(acc, q, rr, D, std::make_integer_sequence<int, 35>{});
-                    } else if constexpr (!T::adjoint) {
+                    } else if constexpr (!T::adjoint && !T::fe) {
                         // L_a, |a| + |b| <= 3
                         double G[20];
                         green<3>(rx, ry, rz, G);
@@ -847,7 +860,19 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         }
         if (half == 1) continue;  // the next pass (none after the last)
     }
-    if constexpr (!T::adjoint) {
+    if constexpr (MODE == MODE_FS_STORE) {
+        // L from F; the saved sums C'_g (1 <= |g| <= 4, total order 4) =
+        // F_g + E_g for |g| <= 3, E_g for |g| = 4, in kept slots (F's kept
+        // slot k + 1 and C's kept slot k are the same multi-index)
+        double L[20];
+        expand<0>(acc, L, std::make_integer_sequence<int, 20>{});
+        const long b = p.out_blk ? p.out_blk[owner] : owner;
+        const long ob = b * kSub3 + cell;
+#pragma unroll
+        for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = L[a];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) p.out1[k * p.out_stride + ob] = k < 15 ? acc[k + 1] + acc[16 + k] : acc[16 + k];
+    } else if constexpr (!T::adjoint) {
         double L[20];
         if constexpr (MODE == MODE_MONO_HALO) {
 #pragma unroll
@@ -892,6 +917,24 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
             scale_inv_fact(F, std::make_integer_sequence<int, 20>{});  // gM_b = F_b / b!
 #pragma unroll
             for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = F[a];
+            if constexpr (MODE == MODE_B2S_STORE) {
+                // the target role of the owner's cells, from the sums the
+                // forward saved: gX_k += sum_a w_a C'_{a+e_k}
+                const int t = p.store_tgt[owner];
+                if (t >= 0) {
+                    const long tb = (long)t * kSub3 + cell;
+                    double Ck[24], Cf[34], w[20];
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) Ck[k] = p.save[k * p.aux_stride2 + tb];
+                    expand<1>(Ck, Cf, std::make_integer_sequence<int, 34>{});
+#pragma unroll
+                    for (int a = 0; a < 20; ++a) w[a] = p.aux2[a * p.aux_stride2 + tb];
+                    double gt[3] = {0.0, 0.0, 0.0};
+                    grad_x(w, Cf, gt, std::make_integer_sequence<int, 20>{});
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) gx[k] += gt[k];
+                }
+            }
 #pragma unroll
             for (int k = 0; k < 3; ++k) p.out1[k * p.out_stride + ob] = gx[k];
         } else {

@@ -11,6 +11,7 @@ sys.path.insert(0, os.path.dirname(__file__))
 import oracle  # noqa: E402
 import synthetic  # noqa: E402
 from parity import assert_parity  # noqa: E402
+from saved_sums import check_saved  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -339,6 +340,15 @@ def test_config4_adjoint_full_and_fd():
     gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w)
     print("config4 gM worst", assert_parity(gM_h, gM_ref, TOL, what="config4 gM"))
     print("config4 gX worst", assert_parity(gX_h, gX_ref, TOL, what="config4 gX"))
+    # the one-pass adjoint from the sums its forward saved, on the same reference
+    Ls = torch.empty((20, batch["T"] * 512), dtype=torch.float64, device="cuda")
+    Cs = torch.empty((24, batch["T"] * 512), dtype=torch.float64, device="cuda")
+    plan.multipole_batched_save(Md, Xd, Ls, Cs)
+    gM2, gX2 = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_saved(Md, Xd, wd, Cs, gM2, gX2)
+    del Ls, Cs
+    print("config4 one-pass gM worst", assert_parity(_host(gM2), gM_ref, TOL, what="config4 one-pass gM"))
+    print("config4 one-pass gX worst", assert_parity(_host(gX2), gX_ref, TOL, what="config4 one-pass gX"))
 
     # central differences of the GPU forward
     rng = np.random.default_rng(4)
@@ -376,9 +386,11 @@ def test_config4_adjoint_full_and_fd():
 
 def test_config5_step_graph_sampled():
     """32^3 sub-grids (16.8M cells), periodic, 20% missing: the benchmark's
-    launch configuration (autotuned schedules, captured forward+adjoint graph)
-    with 256 seeded targets and the same 256 store sub-grids (half of them
-    with missing neighbours) checked against the oracle."""
+    launch configurations (autotuned schedules; the captured two-launch step
+    -- forward with saved sums, one-pass adjoint -- and the captured
+    three-launch step) with 256 seeded targets and the same 256 store
+    sub-grids (half of them with missing neighbours) checked against the
+    oracle, and the saved sums of 16 of those targets."""
     import torch
     import paper_2303_08058_amd as ot
     batch, M, X = synthetic.config5()
@@ -406,14 +418,35 @@ def test_config5_step_graph_sampled():
     sidx = torch.from_numpy(ssel).long().cuda()
     gMs = gM.reshape(20, -1, 512)[:, sidx].reshape(20, -1).cpu().numpy()
     gXs = gX.reshape(3, -1, 512)[:, sidx].reshape(3, -1).cpu().numpy()
-    del L, gM, gX
+    # the two-launch step the benchmark times, on the same buffers
+    Cs = torch.empty((24, NT), dtype=torch.float64, device="cuda")
+    sf, sb = plan.autotune_saved(Md, Xd, L, Cs, wd, gM, gX)
+    print("config5: two-launch step autotuned 0x%x 0x%x" % (sf, sb), flush=True)
+    plan.step_graph_create_saved(Md, Xd, L, Cs, wd, gM, gX, sf, sb)
+    for t in (L, Cs, gM, gX):
+        t.fill_(float("nan"))
+    plan.step_graph_launch()
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(L).all()) and bool(torch.isfinite(gM).all()) and bool(torch.isfinite(gX).all())
+    assert bool(torch.isfinite(Cs).all())
+    Ls2 = L.reshape(20, -1, 512)[:, idx].reshape(20, -1).cpu().numpy()
+    gMs2 = gM.reshape(20, -1, 512)[:, sidx].reshape(20, -1).cpu().numpy()
+    gXs2 = gX.reshape(3, -1, 512)[:, sidx].reshape(3, -1).cpu().numpy()
+    csel = sel[::16]
+    Css = Cs.reshape(24, -1, 512)[:, torch.from_numpy(csel).long().cuda()].reshape(24, -1).cpu().numpy()
+    del L, gM, gX, Cs
     print("config5: oracle forward of 256 targets ...", flush=True)
     ref, A = oracle.batched_forward(batch, M, X, tsel=sel, want_abs=True)
     assert_parity(Ls, ref, TOL, what="config5 L", A=A)
+    assert_parity(Ls2, ref, TOL, what="config5 two-launch L", A=A)
     print("config5: oracle gradient of 256 store sub-grids ...", flush=True)
     gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=ssel)
     print("config5 gM worst", assert_parity(gMs, gM_ref, TOL, what="config5 gM"))
     print("config5 gX worst", assert_parity(gXs, gX_ref, TOL, what="config5 gX"))
+    print("config5 two-launch gM worst", assert_parity(gMs2, gM_ref, TOL, what="config5 two-launch gM"))
+    print("config5 two-launch gX worst", assert_parity(gXs2, gX_ref, TOL, what="config5 two-launch gX"))
+    print("config5: oracle target-side sums of %d targets ..." % len(csel), flush=True)
+    check_saved(Css, batch, M, X, "config5 saved sums", tsel=csel)
 
 
 # the four (sigma1, sigma2) draws of the 32^3-sub-grid field's recipe
