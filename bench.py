@@ -56,6 +56,10 @@ FLOP_PER_PAIR = {
     # source-role pass (its per-cell epilogue adds the target role)
     "forward_save": 121 + 2 * (84 + 111),    # 511
     "adjoint_saved": 121 + 2 * (84 + 111),   # 511
+    # the forward with the angular-momentum correction: the same pair loop as
+    # the forward with saved sums (a per-cell epilogue contracts the order-4
+    # sums with the target's moments)
+    "forward_amc": 121 + 2 * (84 + 111),     # 511
 }
 
 
@@ -239,6 +243,17 @@ def main():
     kernels.update(kernel_stats(plan.kernel_times()))
     plan.set_timing(False)
     del Cs
+    # the forward with the angular-momentum correction of the force (not part
+    # of the step), with the forward-with-saved-sums schedule
+    dF = torch.empty((3, NT), dtype=torch.float64, device=dev)
+    plan.multipole_batched_amc(Md, Xd, L, dF, sched=sf)
+    plan.set_timing(True)
+    plan.kernel_times()
+    for i in range(args.steps):
+        plan.multipole_batched_amc(Md, Xd, L, dF, sched=sf)
+    kernels.update(kernel_stats(plan.kernel_times()))
+    plan.set_timing(False)
+    del dF
     if fs is None:
         fs = sf  # forward schedule of the two-level step (W8 / W8P2 also serve the plain forward)
     # roofline: the step's two launches together, at the method's 780 FLOP per
@@ -654,6 +669,43 @@ def per_subgrid_comparison(n, ot, synthetic, np, torch, dev):
         res["speedup_vs_%dstream" % nstreams] = round(ms / batched_ms, 2)
         log("per-sub-grid launches on %2d stream(s): %.1f ms (%.1fx slower)"
             % (nstreams, ms, ms / batched_ms))
+    # the same launches captured into one graph (fork / join over the
+    # streams, round-robin), replayed: the per-launch cost without host
+    # dispatch through Python and the runtime
+    Lg = torch.empty_like(Lh)
+    for nstreams in (1, 8, 32):
+        cap = torch.cuda.Stream()
+        side = [torch.cuda.Stream() for _ in range(nstreams - 1)]
+        graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=cap):
+            cur = torch.cuda.current_stream()
+            lanes = [cur] + side
+            for sd in side:
+                sd.wait_stream(cur)
+            for t in range(T):
+                ot.ot_fmm_multipole(Mh[t], Xh[t], Lg[t], stream=lanes[t % nstreams])
+            for sd in side:
+                cur.wait_stream(sd)
+        times = []
+        for _ in range(3):
+            Lg.fill_(float("nan"))
+            g0 = torch.cuda.Event(enable_timing=True)
+            g1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            g0.record()
+            graph.replay()
+            g1.record()
+            torch.cuda.synchronize()
+            times.append(g0.elapsed_time(g1))
+        ms = sorted(times)[1]
+        res["per_subgrid_graph_%dstream_ms" % nstreams] = round(ms, 2)
+        res["speedup_vs_graph_%dstream" % nstreams] = round(ms / batched_ms, 2)
+        res["graph_%dstream_bitwise_equal_to_stream_launches" % nstreams] = bool(torch.equal(Lg, Lh))
+        log("per-sub-grid launches in one graph on %2d stream(s): %.1f ms (%.1fx slower)"
+            % (nstreams, ms, ms / batched_ms))
+        del graph
+    del Lg
     # the same launches as futures completed by event polling (32 pool
     # streams, 4 worker threads polling between tasks), waited for by polling
     Lf = torch.empty_like(Lh)
@@ -720,13 +772,30 @@ def cpu_baseline(batch, M, X, w, seconds, np):
     one = time.perf_counter() - t0
     one_pairs = int(sum(slot_pairs[s] for s in range(27) if nbr[sel[0], s] >= 0))
     log("cpu oracle, one thread: %.1f s" % one)
+    # the single-block workloads, timed in full: monopole and multipole
+    # interaction of one 24^3 halo block (921,088 pairs each)
+    import synthetic
+    blocks = {}
+    for name, b, mom in (("monopole_block", synthetic.monopole_block(1001), "mass"),
+                         ("multipole_block", synthetic.multipole_block(1002), "M")):
+        m = b[mom] if mom == "M" else b[mom][None]
+        t0 = time.perf_counter()
+        oracle.block_forward(m, b["com"])
+        dt = time.perf_counter() - t0
+        blocks[name] = {"pairs": 921088, "s": round(dt, 4), "pairs_per_s": 921088 / dt}
+        log("cpu oracle, %s: %.3f s" % (name, dt))
+    total = sum(slot_pairs[s] for t in range(batch["T"]) for s in range(27) if nbr[t, s] >= 0)
     return {"value": pairs / spent, "unit": "cell-pair interactions/s", "cores": max_threads(),
             "kind": "oracle",
             "sample": "fwd of %d sampled target sub-grids + adjoint of the same %d store "
-                      "sub-grids of the benchmark workload (%d pairs, %.1f s)"
-                      % (used, used, pairs, spent),
+                      "sub-grids of the benchmark workload (%d pairs, %.1f s); its rate, extrapolated "
+                      "by the exact pair count, gives %.0f s for one forward+adjoint step of all %d pairs"
+                      % (used, used, pairs, spent, total * spent / pairs, total),
+            "extrapolated_step_s": round(total * spent / pairs, 1),
             "one_core_value": one_pairs / one,
-            "cpu_model": _cpu_model()}
+            "single_block_forward": blocks,
+            "cpu_model": _cpu_model(),
+            "host_cpus": len(os.sched_getaffinity(0))}
 
 
 def _cpu_model():

@@ -256,6 +256,27 @@ int ot_fmm_multipole_backward_saved(ot_fmm_plan plan, const double* M, const dou
                                     const double* gL, const double* Cs, double* gM, double* gcom,
                                     int sched, void* stream);
 
+/* Forward with the angular-momentum correction of the force (Sec. 2.1 cites
+ * Octo-Tiger's FMM, which conserves angular momentum, without its formulas;
+ * this is a reading fixed by that conservation law). With the total-order
+ * truncation the interaction energy
+ *   E = 1/2 sum_i sum_a (M_a(i)/a!) L_a(i)
+ * is invariant under rotations of positions and moments together, so the
+ * forces F_i = -dE/dX_i and the cells' spin torques
+ *   tau_i,m = -sum_{|g| <= 2} eps_mnl (M_{g+e_n}(i)/g!) L_{g+e_l}(i)
+ * satisfy sum_i (X_i x F_i + tau_i) = 0 over a closed set. The force
+ * evaluated from L (ot_fmm_evaluate) misses the terms of -dE/dX_i with
+ * |a| + |b| = 3, and with it the balance fails; this call returns L as
+ * ot_fmm_multipole_batched and those terms,
+ *   dF_k(i) = -sum_{j in S(i)} sum_{|a|+|b| = 3} (M_a(i)/a!) s_b M_b(j) G_{a+b+e_k}(X_i - X_j),
+ * dF[3][T*512] (overwritten): F_i = (force from L) + dF_i conserves linear
+ * and total angular momentum to rounding. With the dipoles about the centres
+ * of mass zero, dF holds the target's mass times the sources' octupoles and
+ * the target's octupole times the sources' masses.
+ * Schedules, errors and overlap rules as for ot_fmm_multipole_batched_save. */
+int ot_fmm_multipole_batched_amc(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                 double* dF, int sched, void* stream);
+
 /* Times both passes of the two-pass step with every schedule (W8, W8P2, each
  * with the four flag combinations) on the given buffers and keeps the fastest
  * in the plan (used by AUTO); leaves the results of the chosen schedules in
@@ -296,9 +317,10 @@ int ot_fmm_step_graph_launch(ot_fmm_plan plan, void* stream);
  * bracketed by HIP events on its stream. ot_fmm_plan_kernel_times waits for
  * the recorded events, returns for each kernel -- [0] batched forward,
  * [1] adjoint source-role pass, [2] adjoint target-role pass, [3] forward
- * with saved sums, [4] one-pass adjoint -- the summed duration in ms and the
- * number of launches, and resets the counters. */
-#define OT_FMM_NKERNELS 5
+ * with saved sums, [4] one-pass adjoint, [5] forward with the
+ * angular-momentum correction -- the summed duration in ms and the number of
+ * launches, and resets the counters. */
+#define OT_FMM_NKERNELS 6
 int ot_fmm_plan_timing(ot_fmm_plan plan, int enable);
 int ot_fmm_plan_kernel_times(ot_fmm_plan plan, double ms_total[OT_FMM_NKERNELS],
                              int64_t launches[OT_FMM_NKERNELS]);

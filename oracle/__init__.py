@@ -60,7 +60,8 @@ def _load():
     for f in (lib.orc_block_forward, lib.orc_block_forward_full):
         f.argtypes = [P, i, P, i, P, P, i]
         f.restype = i
-    for f in (lib.orc_batched_forward, lib.orc_batched_forward_full, lib.orc_batched_forward_tgrad):
+    for f in (lib.orc_batched_forward, lib.orc_batched_forward_full, lib.orc_batched_forward_tgrad,
+              lib.orc_batched_forward_amc):
         f.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
         f.restype = i
     for f in (lib.orc_batched_forward_cs, lib.orc_batched_forward_cs_full,
@@ -189,6 +190,24 @@ def batched_forward_tgrad(batch, M, X, tsel=None, want_abs: bool = False, nthrea
     if rc:
         raise ValueError("orc_batched_forward_tgrad rejected its arguments")
     return (D, A) if want_abs else D
+
+
+def batched_forward_amc(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0):
+    """Angular-momentum correction of the force of each target cell, the
+    terms of -dE/dX_i with |a| + |b| = 3 that the force evaluated from L
+    lacks. Returns dF (3, nsel*512) (and A, the term magnitudes, if want_abs)."""
+    S, T, tgt, nbr, shift, period = _batch_args(batch)
+    tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
+    M = _f64(M)
+    X = _f64(X)
+    assert M.shape == (NM, S * SUB3) and X.shape == (3, S * SUB3)
+    dF = np.zeros((3, len(tsel) * SUB3), np.float64)
+    A = np.zeros_like(dF) if want_abs else None
+    rc = _load().orc_batched_forward_amc(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M),
+                                         _ptr(X), _ptr(tsel), len(tsel), _ptr(dF), _ptr(A), nthreads)
+    if rc:
+        raise ValueError("orc_batched_forward_amc rejected its arguments")
+    return (dF, A) if want_abs else dF
 
 
 def batched_forward_cs(batch, M, Xre, Xim, tsel=None, nthreads: int = 0, full: bool = False):

@@ -544,6 +544,88 @@ int orc_batched_forward_tgrad(int S, int T, const int32_t *tgt, const int32_t *n
     return 0;
 }
 
+/* Angular-momentum correction of the force (a reading; Sec. 2.1 cites the
+ * FMM without its formulas). With the total-order truncation the pair energy
+ *   e_ij = sum_{|a|+|b| <= 3} (M_a(i)/a!) s_b M_b(j) G_{a+b}(X_i - X_j)
+ * is invariant under rotations of positions and moments together, so the
+ * forces F_i = -dE/dX_i and the spin torques of the cells,
+ *   tau_i,m = -sum_{|g| <= 2} eps_mnl (M_{g+e_n}(i)/g!) L_{g+e_l}(i),
+ * balance: sum_i (X_i x F_i + tau_i) = 0, as sum_i F_i = 0. The force
+ * evaluated from L alone, -sum_{|a| <= 2} (M_a/a!) L_{a+e_k}, is the gradient
+ * of the energy truncated one order lower and misses the terms of
+ * -dE/dX_i with |a| + |b| = 3; the correction adds them:
+ *   dF_k(i) = -sum_{j in S(i)} sum_{|a|+|b| = 3} (M_a(i)/a!) s_b M_b(j) G_{a+b+e_k}(X_i - X_j).
+ * Output dF[3][nsel*512] for targets tsel; Aabs (may be NULL): the sums of the
+ * magnitudes of the terms. */
+static double multi_factorial(int g) { return factorial(g_exp[g][0]) * factorial(g_exp[g][1]) * factorial(g_exp[g][2]); }
+
+static void pair_amc(const double Xi[3], const double *Mi, const double Xj[3], const double *Mj, double *dF,
+                     double *Aabs)
+{
+    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
+    double G[NG];
+    green_re(r, 4, G);
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < NM; ++a)
+            for (int b = 0; b < NM; ++b) {
+                if (order_of(a) + order_of(b) != 3) continue;
+                double ma = Mi[a] / multi_factorial(a); /* M_a / a! */
+                double term = -ma * taylor_sign(b) * Mj[b] * G[sum_index(sum_index(a, b), 1 + k)];
+                dF[k] += term;
+                if (Aabs) Aabs[k] += fabs(term);
+            }
+}
+
+int orc_batched_forward_amc(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
+                            const double *period, const double *M, const double *X, const int32_t *tsel,
+                            int nsel, double *dF, double *Aabs, int nthreads)
+{
+    init_tables();
+    if (check_batch(S, T, tgt, nbr)) return -1;
+    for (int q = 0; q < nsel; ++q)
+        if (tsel[q] < 0 || tsel[q] >= T) return -1;
+    const size_t NS = (size_t)S * SUB3;
+    const size_t NO = (size_t)nsel * SUB3;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int q = 0; q < nsel; ++q)
+        for (int ci = 0; ci < SUB3; ++ci) {
+            int t = tsel[q];
+            int li[3];
+            local_coords(ci, li);
+            int hi[3] = {li[0] + 8, li[1] + 8, li[2] + 8};
+            size_t iidx = (size_t)tgt[t] * SUB3 + ci;
+            double Xi[3] = {X[iidx], X[NS + iidx], X[2 * NS + iidx]};
+            double Mi[NM];
+            for (int a = 0; a < NM; ++a) Mi[a] = M[a * NS + iidx];
+            double acc[3] = {0}, aabs[3] = {0};
+            for (int slot = 0; slot < 27; ++slot) {
+                int blk = nbr[t * 27 + slot];
+                if (blk < 0) continue;
+                int so[3];
+                slot_coords(slot, so);
+                double sh[3];
+                neighbour_shift(shift, period, t, slot, sh);
+                for (int cj = 0; cj < SUB3; ++cj) {
+                    int lj[3];
+                    local_coords(cj, lj);
+                    int hj[3] = {8 * so[0] + lj[0], 8 * so[1] + lj[1], 8 * so[2] + lj[2]};
+                    if (!in_stencil(hi, hj)) continue;
+                    size_t jidx = (size_t)blk * SUB3 + cj;
+                    double Xj[3] = {X[jidx] + sh[0], X[NS + jidx] + sh[1], X[2 * NS + jidx] + sh[2]};
+                    double Mj[NM];
+                    for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
+                    pair_amc(Xi, Mi, Xj, Mj, acc, Aabs ? aabs : NULL);
+                }
+            }
+            for (int k = 0; k < 3; ++k) {
+                dF[k * NO + (size_t)q * SUB3 + ci] = acc[k];
+                if (Aabs) Aabs[k * NO + (size_t)q * SUB3 + ci] = aabs[k];
+            }
+        }
+    return 0;
+}
+
 /* Coarse substitute for missing neighbours -- a reading: the paper gives no
  * FMM formulas; at a refinement boundary an FMM lets fine cells interact with
  * the coarser cells that cover a region holding no fine cells.

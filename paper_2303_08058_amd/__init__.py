@@ -93,6 +93,8 @@ _lib.ot_fmm_plan_kernel_times.argtypes = [_P, _P, _P]
 _lib.ot_fmm_plan_kernel_times.restype = _I
 _lib.ot_fmm_multipole_batched_save.argtypes = [_P, _P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_batched_save.restype = _I
+_lib.ot_fmm_multipole_batched_amc.argtypes = [_P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_batched_amc.restype = _I
 _lib.ot_fmm_multipole_backward_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_backward_saved.restype = _I
 _lib.ot_fmm_autotune_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -143,7 +145,7 @@ for _n in ("executor_create", "executor_destroy", "executor_stream", "executor_g
            "future_release"):
     getattr(_lib, "ot_fmm_" + _n).restype = _I
 
-KERNELS = ("forward", "adjoint_source", "adjoint_target", "forward_save", "adjoint_saved")
+KERNELS = ("forward", "adjoint_source", "adjoint_target", "forward_save", "adjoint_saved", "forward_amc")
 NSAVED = 24  # saved target-side sums per target cell (ot_fmm_multipole_batched_save)
 
 
@@ -344,6 +346,15 @@ class Plan:
             _dptr(Cs, (NSAVED, sl[1]), "Cs"), int(sched), _stream(stream)), "ot_fmm_multipole_batched_save")
         return L, Cs
 
+    def multipole_batched_amc(self, M, com, L, dF, sched=SCHED_AUTO, stream=None):
+        """Forward (L) and the angular-momentum correction dF (3, T*512) of
+        each target cell's force."""
+        sm, sx, sl = self._shapes()
+        _check(_lib.ot_fmm_multipole_batched_amc(
+            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+            _dptr(dF, (3, sl[1]), "dF"), int(sched), _stream(stream)), "ot_fmm_multipole_batched_amc")
+        return L, dF
+
     def multipole_backward_saved(self, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None):
         """One-pass adjoint from the sums of multipole_batched_save (gM, gcom overwritten)."""
         sm, sx, sl = self._shapes()
@@ -428,6 +439,10 @@ def ot_fmm_multipole_batched_save(plan, M, com, L, Cs, sched=SCHED_AUTO, stream=
 
 def ot_fmm_multipole_backward_saved(plan, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None):
     return plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom, sched, stream)
+
+
+def ot_fmm_multipole_batched_amc(plan, M, com, L, dF, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_batched_amc(M, com, L, dF, sched, stream)
 
 
 def ot_fmm_plan_set_coarse(plan, Sp, coarse, octant):

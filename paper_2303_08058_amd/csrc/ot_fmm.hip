@@ -162,7 +162,7 @@ constexpr int kFullSched = OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT | OT_FMM_
 constexpr int kSaveSched = OT_FMM_SCHED_W8P2 | OT_FMM_SCHED_PERSISTENT | OT_FMM_SCHED_LOCAL;
 
 // kernels timed by the plan's events (ot_fmm_plan_kernel_times)
-constexpr int kTimedKernels = 5;
+constexpr int kTimedKernels = OT_FMM_NKERNELS;
 
 int pick_fwd(int sched, int tuned)
 {
@@ -211,10 +211,11 @@ struct ot_fmm_plan_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // per-kernel timing (forward, adjoint source pass, adjoint target pass,
-    // forward with saved sums, one-pass adjoint)
+    // forward with saved sums, one-pass adjoint, forward with the
+    // angular-momentum correction)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[kTimedKernels];
-    size_t ev_used[kTimedKernels] = {0, 0, 0, 0, 0};
+    size_t ev_used[kTimedKernels] = {};
     // coarse substitutes for missing neighbours (ot_fmm_plan_set_coarse)
     std::vector<uint32_t> missing;  // [T] bit s: slot s has no fine neighbour
     int32_t Sp_coarse = 0;
@@ -521,6 +522,37 @@ int fwd_save_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
     if (shape == OT_FMM_SCHED_W8P2)
         return launch_timed<MODE_FS_STORE, 8, 2>(plan, 3, kp, plan->T, pers, stream);
     return fail(OT_FMM_EINVAL, "unknown schedule for the forward with saved sums");
+}
+
+// Forward with the angular-momentum correction of the force: L, and
+// dF_k(i) = -sum_{j in S(i)} sum_{|a|+|b| = 3} (M_a(i)/a!) s_b M_b(j) G_{a+b+e_k}(X_i - X_j),
+// [3][T*512]. Same pair loop as the forward with saved sums.
+int fwd_amc_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, double* dF, int sched,
+                    hipStream_t stream)
+{
+    KParams kp{};
+    kp.mom = M;
+    kp.pos = com;
+    kp.mom_stride = (long)plan->S * kSub3;
+    kp.pos_stride = (long)plan->S * kSub3;
+    kp.rel = plan->d_fwd_rel;
+    kp.own_blk = plan->d_tgt;
+    kp.order = plan->d_fwd_order;
+    kp.aux = M;
+    kp.aux_stride = (long)plan->S * kSub3;
+    kp.out0 = L;
+    kp.out1 = dF;
+    kp.out_stride = (long)plan->T * kSub3;
+    kp.out_blk = nullptr;
+    for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
+    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_save ? plan->tuned_save : kSaveSched;
+    const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
+    apply_order(kp, plan, sched, false);
+    const int shape = sched & kShapeMask;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_AMC_STORE, 8>(plan, 5, kp, plan->T, pers, stream);
+    if (shape == OT_FMM_SCHED_W8P2)
+        return launch_timed<MODE_AMC_STORE, 8, 2>(plan, 5, kp, plan->T, pers, stream);
+    return fail(OT_FMM_EINVAL, "unknown schedule for the forward with the angular-momentum correction");
 }
 
 // One-pass adjoint from the saved sums: the source-role pass over every store
@@ -1357,6 +1389,23 @@ int ot_fmm_multipole_batched_save(ot_fmm_plan plan, const double* M, const doubl
         return fail(OT_FMM_EINVAL, "the saved sums overlap an input or L");
     if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
     return fwd_save_batched(plan, M, com, L, Cs, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole_batched_amc(ot_fmm_plan plan, const double* M, const double* com, double* L, double* dF,
+                                 int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned16(M) || !aligned16(com) || !aligned16(L) || !aligned16(dF))
+        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    if (overlap(dF, 3 * NT, M, 20 * NS) || overlap(dF, 3 * NT, com, 3 * NS) || overlap(dF, 3 * NT, L, 20 * NT))
+        return fail(OT_FMM_EINVAL, "dF overlaps an input or L");
+    if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
+    return fwd_amc_batched(plan, M, com, L, dF, sched, (hipStream_t)stream);
 }
 
 // Extents rule of the one-pass adjoint: gM and gcom overlap no input and not

@@ -214,46 +214,40 @@ __device__ __forceinline__ void green(double x, double y, double z, double* G)
     G[6] = x * zD2;
     G[7] = __builtin_fma(y, yD2, D1);
     G[8] = y * zD2;
-    G[9] = __builtin_fma(z, zD2, D1);
     const double xD3 = x * D3, yD3 = y * D3, zD3 = z * D3;
     const double xx3 = x * xD3, xy3 = x * yD3, xz3 = x * zD3;
-    const double yy3 = y * yD3, yz3 = y * zD3, zz3 = z * zD3;
+    const double yy3 = y * yD3, yz3 = y * zD3;
     G[10] = __builtin_fma(x, xx3, 3.0 * xD2);  // xxx
     G[11] = __builtin_fma(y, xx3, yD2);        // xxy
     G[12] = __builtin_fma(z, xx3, zD2);        // xxz
     G[13] = __builtin_fma(x, yy3, xD2);        // xyy
     G[14] = z * xy3;                           // xyz
-    G[15] = __builtin_fma(x, zz3, xD2);        // xzz
     G[16] = __builtin_fma(y, yy3, 3.0 * yD2);  // yyy
     G[17] = __builtin_fma(z, yy3, zD2);        // yyz
-    G[18] = __builtin_fma(y, zz3, yD2);        // yzz
-    G[19] = __builtin_fma(z, zz3, 3.0 * zD2);  // zzz
+    // components with z^2 from the trace (Laplace: G_{g+xx} + G_{g+yy} + G_{g+zz} = 0)
+    G[9] = -(G[4] + G[7]);     // zz
+    G[15] = -(G[10] + G[13]);  // xzz
+    G[18] = -(G[11] + G[16]);  // yzz
+    G[19] = -(G[12] + G[17]);  // zzz
     if constexpr (ORD >= 4) {
         const double D4 = -7.0 * D3 * ri2;
-        const double xD4 = x * D4, yD4 = y * D4, zD4 = z * D4;
-        const double xx4 = x * xD4, xy4 = x * yD4, xz4 = x * zD4;
-        const double yy4 = y * yD4, yz4 = y * zD4, zz4 = z * zD4;
-        G[20] = __builtin_fma(x * x, xx4, __builtin_fma(6.0, xx3, 3.0 * D2));            // xxxx
-        G[21] = __builtin_fma(x * y, xx4, 3.0 * xy3);                                   // xxxy
-        G[22] = __builtin_fma(x * z, xx4, 3.0 * xz3);                                   // xxxz
-        G[23] = __builtin_fma(y * y, xx4, __builtin_fma(1.0, xx3 + yy3, D2));           // xxyy
-        G[24] = __builtin_fma(y * z, xx4, yz3);                                         // xxyz
-        G[25] = __builtin_fma(z * z, xx4, __builtin_fma(1.0, xx3 + zz3, D2));           // xxzz
-        G[26] = __builtin_fma(x * y, yy4, 3.0 * xy3);                                   // xyyy
-        G[27] = __builtin_fma(x * z, yy4, xz3);                                         // xyyz
-        G[28] = __builtin_fma(x * y, zz4, xy3);                                         // xyzz
-        G[29] = __builtin_fma(x * z, zz4, 3.0 * xz3);                                   // xzzz
-        G[30] = __builtin_fma(y * y, yy4, __builtin_fma(6.0, yy3, 3.0 * D2));           // yyyy
-        G[31] = __builtin_fma(y * z, yy4, 3.0 * yz3);                                   // yyyz
-        G[32] = __builtin_fma(z * z, yy4, __builtin_fma(1.0, yy3 + zz3, D2));           // yyzz
-        G[33] = __builtin_fma(y * z, zz4, 3.0 * yz3);                                   // yzzz
-        G[34] = __builtin_fma(z * z, zz4, __builtin_fma(6.0, zz3, 3.0 * D2));           // zzzz
-        (void)xD4;
-        (void)yD4;
-        (void)zD4;
-        (void)xy4;
-        (void)xz4;
-        (void)yz4;
+        const double xD4 = x * D4, yD4 = y * D4;
+        const double xx4 = x * xD4, yy4 = y * yD4;
+        G[20] = __builtin_fma(x * x, xx4, __builtin_fma(6.0, xx3, 3.0 * D2));  // xxxx
+        G[21] = __builtin_fma(x * y, xx4, 3.0 * xy3);                         // xxxy
+        G[22] = __builtin_fma(x * z, xx4, 3.0 * xz3);                         // xxxz
+        G[23] = __builtin_fma(y * y, xx4, __builtin_fma(1.0, xx3 + yy3, D2)); // xxyy
+        G[24] = __builtin_fma(y * z, xx4, yz3);                               // xxyz
+        G[26] = __builtin_fma(x * y, yy4, 3.0 * xy3);                         // xyyy
+        G[27] = __builtin_fma(x * z, yy4, xz3);                               // xyyz
+        G[30] = __builtin_fma(y * y, yy4, __builtin_fma(6.0, yy3, 3.0 * D2)); // yyyy
+        G[31] = __builtin_fma(y * z, yy4, 3.0 * yz3);                         // yyyz
+        G[25] = -(G[20] + G[23]);  // xxzz
+        G[28] = -(G[21] + G[26]);  // xyzz
+        G[29] = -(G[22] + G[27]);  // xzzz
+        G[32] = -(G[23] + G[30]);  // yyzz
+        G[33] = -(G[24] + G[31]);  // yzzz
+        G[34] = -(G[25] + G[32]);  // zzzz
     }
 }
 
@@ -480,8 +474,10 @@ enum Mode : int {
     MODE_B2F_STORE = 6,   // adjoint of the full truncation, source role -> gM, gX (overwrite)
     MODE_B1F_STORE = 7,   // adjoint of the full truncation, target role -> gX (accumulate)
     MODE_FS_STORE = 8,    // batched forward -> L, plus the target-role sums the adjoint needs
-    MODE_B2S_STORE = 9    // adjoint from those sums: source role per store sub-grid, plus the
+    MODE_B2S_STORE = 9,   // adjoint from those sums: source role per store sub-grid, plus the
                           // target role of its cells from the saved sums -> gM, gX (overwrite)
+    MODE_AMC_STORE = 10   // batched forward -> L, plus the angular-momentum correction of the
+                          // force of each target cell -> dF
 };
 
 constexpr int kMaxPieces = 16;  // work-list pieces (one per XCD) of a persistent launch
@@ -504,7 +500,7 @@ struct KParams {
     const double* save;
     long aux_stride2;
     double* out0;          // L, or gM (B2), or gX (B1)
-    double* out1;          // gX (B2), or the saved target-role sums (FS)
+    double* out1;          // gX (B2), the saved target-role sums (FS) or the force correction (AMC)
     long out_stride;
     const int* out_blk;    // owner -> output block (NULL: identity)
     double period[3];
@@ -527,7 +523,8 @@ struct ModeTraits {
                                      MODE == MODE_B1F_STORE || MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE);
     static constexpr bool source_role = (MODE == MODE_B2_STORE || MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE);
     // the F + E sums (total order 3, and the order-4 terms of orders 1..4)
-    static constexpr bool fe = (MODE == MODE_B2_STORE || MODE == MODE_B2S_STORE || MODE == MODE_FS_STORE);
+    static constexpr bool fe = (MODE == MODE_B2_STORE || MODE == MODE_B2S_STORE || MODE == MODE_FS_STORE ||
+                                MODE == MODE_AMC_STORE);
     // accumulators: monopole 20; forward 16 kept of 20; target-role adjoint
     // 24 kept of the 34 orders 1..4; source-role adjoint and the forward
     // with saved sums 16 + 24; with the full truncation the source role keeps
@@ -872,6 +869,26 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = L[a];
 #pragma unroll
         for (int k = 0; k < 24; ++k) p.out1[k * p.out_stride + ob] = k < 15 ? acc[k + 1] + acc[16 + k] : acc[16 + k];
+    } else if constexpr (MODE == MODE_AMC_STORE) {
+        // L from F; the force correction dF_k = -sum_{|a| <= 3} (M_a/a!) E_{a+e_k}
+        // (E: the sums of exact total order 4), with the target cell's own moments
+        double L[20];
+        expand<0>(acc, L, std::make_integer_sequence<int, 20>{});
+        const long b = p.out_blk ? p.out_blk[owner] : owner;
+        const long ob = b * kSub3 + cell;
+#pragma unroll
+        for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = L[a];
+        double E[34];
+        expand<1>(acc + 16, E, std::make_integer_sequence<int, 34>{});
+        const long mb = (p.own_blk ? p.own_blk[owner] : owner) * (long)kSub3 + cell;
+        double c[20];
+#pragma unroll
+        for (int a = 0; a < 20; ++a) c[a] = p.aux[a * p.aux_stride + mb];
+        scale_inv_fact(c, std::make_integer_sequence<int, 20>{});
+        double gx[3] = {0.0, 0.0, 0.0};
+        grad_x(c, E, gx, std::make_integer_sequence<int, 20>{});
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p.out1[k * p.out_stride + ob] = -gx[k];
     } else if constexpr (!T::adjoint) {
         double L[20];
         if constexpr (MODE == MODE_MONO_HALO) {
