@@ -24,7 +24,7 @@
  *   - Component order of all 20-vectors: graded lexicographic, x most
  *     significant: 1; x,y,z; xx,xy,xz,yy,yz,zz; xxx,xxy,xxz,xyy,xyz,xzz,yyy,
  *     yyz,yzz,zzz. Arrays are structure-of-arrays: component-major.
- *   - All double pointers are DEVICE pointers (FP64, 16-byte aligned), owned by
+ *   - All double pointers are DEVICE pointers (FP64, 8-byte aligned), owned by
  *     the caller. The library keeps no reference to them after a call returns,
  *     except inside a captured step graph (ot_fmm_step_graph_create).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). The
@@ -184,7 +184,7 @@ int ot_fmm_plan_set_coarse(ot_fmm_plan plan, int32_t Sp, const int32_t* coarse, 
 
 /* Adds the coarse contributions into L[20][T*512]: com[3][S*512] (the fine
  * centres of the targets), Mp[20][Sp*512], comp[3][Sp*512] the coarse store
- * (e.g. from ot_fmm_m2m); device pointers, 16-byte aligned, caller-owned.
+ * (e.g. from ot_fmm_m2m); device pointers, 8-byte aligned, caller-owned.
  * EINVAL: no tables set, a null or misaligned pointer, L overlapping an input
  * (nothing enqueued). Enqueue only, on `stream`; targets without substitutes
  * are left untouched. */
@@ -338,7 +338,7 @@ typedef struct ot_fmm_tree_s* ot_fmm_tree;
 /* children: HOST array [Sp][8] of child store ids in [0, Sc), each id at most
  * once, 8*Sp <= 2^26 (EINVAL otherwise). Keeps a device copy; synchronous;
  * bound to the current device (passes on another device return EINVAL).
- * All device pointers of the passes: 16-byte aligned (EINVAL otherwise);
+ * All device pointers of the passes: 8-byte aligned (EINVAL otherwise);
  * the passes are asynchronous on `stream`, and outputs must not alias inputs. */
 int ot_fmm_tree_create(int32_t Sp, int32_t Sc, const int32_t* children, ot_fmm_tree* out);
 int ot_fmm_tree_destroy(ot_fmm_tree tree);

@@ -369,8 +369,8 @@ int ot_fmm_executor_multipole_async(ot_fmm_executor ex, const double* M, const d
     g_last_error.clear();
     if (!ex || !out) return fail(OT_FMM_EINVAL, "null executor or output pointer");
     *out = nullptr;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int i = (int)(ex->next_stream.fetch_add(1, std::memory_order_relaxed) % ex->nstreams);
     hipStream_t s = nullptr;
     int rc = pool_stream(ex, i, &s);

@@ -107,9 +107,11 @@ static_assert(check_indices(), "multi-index tables");
 // Device set-up check: the current device is a gfx950 (one check per device).
 int ensure_device();
 
-inline bool aligned16(const void* p)
+// A double array's natural alignment: the kernels read and write global
+// memory one double at a time.
+inline bool aligned8(const void* p)
 {
-    return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0;
+    return p && (reinterpret_cast<uintptr_t>(p) & 7u) == 0;
 }
 
 // Copies a host table to a new device allocation (ENOMEM / EHIP on failure;

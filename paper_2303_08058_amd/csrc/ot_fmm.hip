@@ -941,8 +941,8 @@ const char* ot_fmm_last_error(void) { return g_last_error.c_str(); }
 int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stream)
 {
     g_last_error.clear();
-    if (!aligned16(mass) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(mass) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     if (overlap(L, 20 * kSub3, mass, kHalo3) || overlap(L, 20 * kSub3, com, 3 * kHalo3))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
     int rc = ensure_device();
@@ -957,8 +957,8 @@ int ot_fmm_monopole(const double* mass, const double* com, double* L, void* stre
 int ot_fmm_multipole(const double* M, const double* com, double* L, void* stream)
 {
     g_last_error.clear();
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     if (overlap(L, 20 * kSub3, M, 20 * kHalo3) || overlap(L, 20 * kSub3, com, 3 * kHalo3))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
     int rc = ensure_device();
@@ -1230,8 +1230,8 @@ static int coarse_fine_any(bool full, ot_fmm_plan plan, const double* com, const
     int rc = check_plan(plan);
     if (rc) return rc;
     if (plan->Sp_coarse <= 0) return fail(OT_FMM_EINVAL, "no coarse substitutes set (ot_fmm_plan_set_coarse)");
-    if (!aligned16(com) || !aligned16(Mp) || !aligned16(comp) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(com) || !aligned8(Mp) || !aligned8(comp) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3,
                   NP = (int64_t)plan->Sp_coarse * kSub3;
     if (overlap(L, 20 * NT, com, 3 * NS) || overlap(L, 20 * NT, Mp, 20 * NP) || overlap(L, 20 * NT, comp, 3 * NP))
@@ -1306,8 +1306,8 @@ int ot_fmm_multipole_batched(ot_fmm_plan plan, const double* M, const double* co
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
     if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
@@ -1321,8 +1321,8 @@ int ot_fmm_multipole_batched_full(ot_fmm_plan plan, const double* M, const doubl
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
     if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
@@ -1337,8 +1337,8 @@ int ot_fmm_multipole_backward(ot_fmm_plan plan, const double* M, const double* c
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(gM) || !aligned16(gcom))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(gL) || !aligned8(gM) || !aligned8(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     {
         const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
         const double* in[3] = {M, com, gL};
@@ -1359,8 +1359,8 @@ int ot_fmm_multipole_backward_full(ot_fmm_plan plan, const double* M, const doub
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(gM) || !aligned16(gcom))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(gL) || !aligned8(gM) || !aligned8(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     {
         const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
         const double* in[3] = {M, com, gL};
@@ -1380,8 +1380,8 @@ int ot_fmm_multipole_batched_save(ot_fmm_plan plan, const double* M, const doubl
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L) || !aligned16(Cs))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L) || !aligned8(Cs))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
     if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
@@ -1397,8 +1397,8 @@ int ot_fmm_multipole_batched_amc(ot_fmm_plan plan, const double* M, const double
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L) || !aligned16(dF))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L) || !aligned8(dF))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
     if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
         return fail(OT_FMM_EINVAL, "L overlaps an input");
@@ -1413,9 +1413,9 @@ int ot_fmm_multipole_batched_amc(ot_fmm_plan plan, const double* M, const double
 static int check_saved_bwd(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
                            const double* Cs, const double* gM, const double* gcom)
 {
-    if (!aligned16(M) || !aligned16(com) || !aligned16(gL) || !aligned16(Cs) || !aligned16(gM) ||
-        !aligned16(gcom))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(gL) || !aligned8(Cs) || !aligned8(gM) ||
+        !aligned8(gcom))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
     const double* in[4] = {M, com, gL, Cs};
     const int64_t nin[4] = {20 * NS, 3 * NS, 20 * NT, 24 * NT};
@@ -1431,7 +1431,7 @@ static int check_saved_bwd(ot_fmm_plan plan, const double* M, const double* com,
 static int check_saved_step(ot_fmm_plan plan, const double* M, const double* com, const double* L,
                             const double* Cs, const double* gL, const double* gM, const double* gcom)
 {
-    if (!aligned16(L)) return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(L)) return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     int rc = check_saved_bwd(plan, M, com, gL, Cs, gM, gcom);
     if (rc) return rc;
     const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
@@ -1544,10 +1544,10 @@ int ot_fmm_autotune(ot_fmm_plan plan, const double* M, const double* com, double
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const bool with_bwd = gL || gM || gcom;
-    if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
+    if (with_bwd && (!aligned8(gL) || !aligned8(gM) || !aligned8(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
     if ((rc = check_overlaps(plan, M, com, L, gL, with_bwd ? gM : nullptr, gcom))) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -1635,10 +1635,10 @@ int ot_fmm_step_graph_create(ot_fmm_plan plan, const double* M, const double* co
     g_last_error.clear();
     int rc = check_plan(plan);
     if (rc) return rc;
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const bool with_bwd = gL || gM || gcom;
-    if (with_bwd && (!aligned16(gL) || !aligned16(gM) || !aligned16(gcom)))
+    if (with_bwd && (!aligned8(gL) || !aligned8(gM) || !aligned8(gcom)))
         return fail(OT_FMM_EINVAL, "null or misaligned backward pointer");
     if (!valid_fwd_sched(fwd_sched)) return fail(OT_FMM_EINVAL, "unknown schedule");
     if (with_bwd && !valid_bwd_sched(bwd_sched))
@@ -1819,8 +1819,8 @@ int ot_fmm_multipole_batched_noalloc(int32_t S, int32_t T, const int32_t* tgt, c
                 return fail(OT_FMM_EINVAL, "period must be finite");
             per[k] = period[k];
         }
-    if (!aligned16(M) || !aligned16(com) || !aligned16(L))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     const int64_t NS = (int64_t)S * kSub3, NT = (int64_t)T * kSub3;
     if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
         return fail(OT_FMM_EINVAL, "L overlaps an input");

@@ -364,8 +364,8 @@ int ot_fmm_m2m(ot_fmm_tree tree, const double* Mc, const double* comc, double* M
     g_last_error.clear();
     int rc = check_tree(tree);
     if (rc) return rc;
-    if (!aligned16(Mc) || !aligned16(comc) || !aligned16(Mp) || !aligned16(comp))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(Mc) || !aligned8(comc) || !aligned8(Mp) || !aligned8(comp))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     {
         const int64_t nc = (int64_t)tree->Sc * kSub3, np = (int64_t)tree->Sp * kSub3;
         if (overlap(Mp, 20 * np, Mc, 20 * nc) || overlap(Mp, 20 * np, comc, 3 * nc) ||
@@ -394,8 +394,8 @@ int ot_fmm_l2l(ot_fmm_tree tree, const double* Lp, const double* comp, const dou
     g_last_error.clear();
     int rc = check_tree(tree);
     if (rc) return rc;
-    if (!aligned16(Lp) || !aligned16(comp) || !aligned16(comc) || !aligned16(Lc))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(Lp) || !aligned8(comp) || !aligned8(comc) || !aligned8(Lc))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     {
         const int64_t nc = (int64_t)tree->Sc * kSub3, np = (int64_t)tree->Sp * kSub3;
         if (overlap(Lc, 20 * nc, Lp, 20 * np) || overlap(Lc, 20 * nc, comp, 3 * np) ||
@@ -423,8 +423,8 @@ int ot_fmm_evaluate(int64_t ncells, const double* M, const double* L, double* F,
 {
     g_last_error.clear();
     if (ncells <= 0 || ncells > ((int64_t)1 << 38)) return fail(OT_FMM_EINVAL, "ncells out of range");
-    if (!aligned16(M) || !aligned16(L) || !aligned16(F) || !aligned16(W))
-        return fail(OT_FMM_EINVAL, "null or misaligned (16-byte) pointer");
+    if (!aligned8(M) || !aligned8(L) || !aligned8(F) || !aligned8(W))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
     if (overlap(F, 3 * ncells, M, 20 * ncells) || overlap(F, 3 * ncells, L, 20 * ncells) ||
         overlap(W, ncells, M, 20 * ncells) || overlap(W, ncells, L, 20 * ncells) || overlap(F, 3 * ncells, W, ncells))
         return fail(OT_FMM_EINVAL, "outputs overlap inputs or each other");
