@@ -15,7 +15,7 @@ sys.path.insert(0, os.path.dirname(__file__))
 import oracle  # noqa: E402
 import synthetic  # noqa: E402
 from parity import assert_parity  # noqa: E402
-from test_oracle_amc import cross, spin_torque  # noqa: E402
+from torque import cross, spin_torque  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
