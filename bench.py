@@ -483,6 +483,10 @@ FULL_FLOP_PLAIN = 1264
 # derivatives the contraction reads: 330; the reduced products: 25 x 16
 # (24 x 16) -> source-role pass 1153, target-role pass 1121
 FULL_ADJ_FLOP_REDUCED = 1153 + 1121
+# the two-launch step of the full truncation: the forward that also keeps the
+# target-side sums runs the source-role pass's pair loop (orders 0..4 from
+# every moment, 1153), and so does the one-pass adjoint
+FULL_SAVED_STEP_FLOP_REDUCED = 1153 + 1153
 
 
 def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None, wd=None, gM=None, gX=None):
@@ -537,6 +541,28 @@ def full_truncation(plan, pairs, steps, Md, Xd, L, ot, torch, sched=None, wd=Non
                           "roofline": {"bound": "alu", "achieved": round(btf, 3), "peak": PEAK_FP64_TFLOPS,
                                        "unit": "TFLOP/s", "frac": round(btf / PEAK_FP64_TFLOPS, 4)}}
         out["fwd_bwd_pairs_per_s"] = pairs / ((ms + bms) * 1e-3)
+        # the two-launch step: forward with saved sums, one-pass adjoint
+        Cs = torch.empty((ot.NSAVED, L.shape[1]), dtype=torch.float64, device=L.device)
+        plan.multipole_batched_save(Md, Xd, L, Cs, full=True)  # warm-up
+        plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, full=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.multipole_batched_save(Md, Xd, L, Cs, full=True)
+            plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, full=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        del Cs
+        sms = e0.elapsed_time(e1) / steps
+        stf = pairs * FULL_SAVED_STEP_FLOP_REDUCED / (sms * 1e-3) / 1e12
+        log("full truncation two-launch step: %.2f ms (three launches %.2f), %.3e pairs/s, %.2f TFLOP/s"
+            " (reduced count)" % (sms, ms + bms, pairs / (sms * 1e-3), stf))
+        out["saved_step"] = {"mean_ms": round(sms, 3), "pairs_per_s": pairs / (sms * 1e-3),
+                             "flop_per_pair": FULL_SAVED_STEP_FLOP_REDUCED,
+                             "roofline": {"bound": "alu", "achieved": round(stf, 3), "peak": PEAK_FP64_TFLOPS,
+                                          "unit": "TFLOP/s", "frac": round(stf / PEAK_FP64_TFLOPS, 4)}}
     return out
 
 

@@ -256,6 +256,19 @@ int ot_fmm_multipole_backward_saved(ot_fmm_plan plan, const double* M, const dou
                                     const double* gL, const double* Cs, double* gM, double* gcom,
                                     int sched, void* stream);
 
+/* The same two-launch step for the full truncation (ot_fmm_multipole_batched_full
+ * and its adjoint): Cs[24][T*512] holds C'_g(i) = sum_{j in S(i)} sum_{|b| <= 3}
+ * s_b M_b(j) G_{g+b}(X_i - X_j), 1 <= |g| <= 4 (= dL_a(i)/dX_i,k under the full
+ * truncation for g = a + e_k; its orders 1..3 equal L), the same 24 kept
+ * components; derivatives of G to order 7. Schedules: W8 or W8P2 with the
+ * flags, AUTO = W8P2 | PERSISTENT | LOCAL (not autotuned); errors and overlap
+ * rules as for the total-order pair. */
+int ot_fmm_multipole_batched_full_save(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                       double* Cs, int sched, void* stream);
+int ot_fmm_multipole_backward_full_saved(ot_fmm_plan plan, const double* M, const double* com,
+                                         const double* gL, const double* Cs, double* gM, double* gcom,
+                                         int sched, void* stream);
+
 /* Forward with the angular-momentum correction of the force (Sec. 2.1 cites
  * Octo-Tiger's FMM, which conserves angular momentum, without its formulas;
  * this is a reading fixed by that conservation law). With the total-order

@@ -61,6 +61,7 @@ def _load():
         f.argtypes = [P, i, P, i, P, P, i]
         f.restype = i
     for f in (lib.orc_batched_forward, lib.orc_batched_forward_full, lib.orc_batched_forward_tgrad,
+              lib.orc_batched_forward_tgrad_full,
               lib.orc_batched_forward_amc):
         f.argtypes = [i, i, P, P, P, P, P, P, P, i, P, P, i]
         f.restype = i
@@ -174,9 +175,11 @@ def batched_forward(batch, M, X, tsel=None, want_abs: bool = False, nthreads: in
     return (L, A) if want_abs else L
 
 
-def batched_forward_tgrad(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0):
+def batched_forward_tgrad(batch, M, X, tsel=None, want_abs: bool = False, nthreads: int = 0,
+                          full: bool = False):
     """Target-side derivatives of the forward, D[a, k] = dL_a(i)/dX_i,k with the
-    sources' centres held fixed, over a selection of targets.
+    sources' centres held fixed, over a selection of targets (full=True: of
+    the full truncation's L).
     Returns D (20, 3, nsel*512) (and A, the term magnitudes, if want_abs)."""
     S, T, tgt, nbr, shift, period = _batch_args(batch)
     tsel = np.arange(T, dtype=np.int32) if tsel is None else _i32(tsel)
@@ -185,7 +188,9 @@ def batched_forward_tgrad(batch, M, X, tsel=None, want_abs: bool = False, nthrea
     assert M.shape == (NM, S * SUB3) and X.shape == (3, S * SUB3)
     D = np.zeros((NM, 3, len(tsel) * SUB3), np.float64)
     A = np.zeros_like(D) if want_abs else None
-    rc = _load().orc_batched_forward_tgrad(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M),
+    lib = _load()
+    fn = lib.orc_batched_forward_tgrad_full if full else lib.orc_batched_forward_tgrad
+    rc = fn(S, T, _ptr(tgt), _ptr(nbr), _ptr(shift), _ptr(period), _ptr(M),
                                            _ptr(X), _ptr(tsel), len(tsel), _ptr(D), _ptr(A), nthreads)
     if rc:
         raise ValueError("orc_batched_forward_tgrad rejected its arguments")

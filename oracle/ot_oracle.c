@@ -480,7 +480,9 @@ int orc_batched_forward_full(int S, int T, const int32_t *tgt, const int32_t *nb
  * (Cell i is never one of its own sources, so this is the whole derivative of
  * L(i) with respect to X_i whenever i's sub-grid appears only in slot 13.)
  * Output D[20][3][nsel*512] for targets tsel; Aabs (may be NULL): the sums of
- * the magnitudes of the terms. */
+ * the magnitudes of the terms.
+ * full != 0: the same derivatives of the full truncation's L (every
+ * |beta| <= 3 for every |alpha| <= 3; derivatives of G to order 7). */
 static void pair_tgrad(const double Xi[3], const double Xj[3], const double *Mj, double *D, double *Aabs)
 {
     double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
@@ -496,11 +498,28 @@ static void pair_tgrad(const double Xi[3], const double Xj[3], const double *Mj,
             }
 }
 
-int orc_batched_forward_tgrad(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
-                              const double *period, const double *M, const double *X, const int32_t *tsel,
-                              int nsel, double *D, double *Aabs, int nthreads)
+static void pair_tgrad_full(const double Xi[3], const double Xj[3], const double *Mj, double *D, double *Aabs)
+{
+    double r[3] = {Xi[0] - Xj[0], Xi[1] - Xj[1], Xi[2] - Xj[2]};
+    double G[NGA];
+    green_general_re(r, 7, G);
+    for (int a = 0; a < NM; ++a)
+        for (int k = 0; k < 3; ++k)
+            for (int b = 0; b < NM; ++b) {
+                int e[3] = {g_exp[a][0] + g_exp[b][0], g_exp[a][1] + g_exp[b][1], g_exp[a][2] + g_exp[b][2]};
+                e[k] += 1;
+                double term = taylor_sign(b) * Mj[b] * G[gidx(e[0], e[1], e[2])];
+                D[a * 3 + k] += term;
+                if (Aabs) Aabs[a * 3 + k] += fabs(term);
+            }
+}
+
+static int batched_forward_tgrad(int full, int S, int T, const int32_t *tgt, const int32_t *nbr,
+                                 const int8_t *shift, const double *period, const double *M, const double *X,
+                                 const int32_t *tsel, int nsel, double *D, double *Aabs, int nthreads)
 {
     init_tables();
+    init_tables6();
     if (check_batch(S, T, tgt, nbr)) return -1;
     for (int q = 0; q < nsel; ++q)
         if (tsel[q] < 0 || tsel[q] >= T) return -1;
@@ -533,7 +552,10 @@ int orc_batched_forward_tgrad(int S, int T, const int32_t *tgt, const int32_t *n
                     double Xj[3] = {X[jidx] + sh[0], X[NS + jidx] + sh[1], X[2 * NS + jidx] + sh[2]};
                     double Mj[NM];
                     for (int b = 0; b < NM; ++b) Mj[b] = M[b * NS + jidx];
-                    pair_tgrad(Xi, Xj, Mj, acc, Aabs ? aabs : NULL);
+                    if (full)
+                        pair_tgrad_full(Xi, Xj, Mj, acc, Aabs ? aabs : NULL);
+                    else
+                        pair_tgrad(Xi, Xj, Mj, acc, Aabs ? aabs : NULL);
                 }
             }
             for (int a = 0; a < NM * 3; ++a) {
@@ -542,6 +564,20 @@ int orc_batched_forward_tgrad(int S, int T, const int32_t *tgt, const int32_t *n
             }
         }
     return 0;
+}
+
+int orc_batched_forward_tgrad(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
+                              const double *period, const double *M, const double *X, const int32_t *tsel,
+                              int nsel, double *D, double *Aabs, int nthreads)
+{
+    return batched_forward_tgrad(0, S, T, tgt, nbr, shift, period, M, X, tsel, nsel, D, Aabs, nthreads);
+}
+
+int orc_batched_forward_tgrad_full(int S, int T, const int32_t *tgt, const int32_t *nbr, const int8_t *shift,
+                                   const double *period, const double *M, const double *X, const int32_t *tsel,
+                                   int nsel, double *D, double *Aabs, int nthreads)
+{
+    return batched_forward_tgrad(1, S, T, tgt, nbr, shift, period, M, X, tsel, nsel, D, Aabs, nthreads);
 }
 
 /* Angular-momentum correction of the force (a reading; Sec. 2.1 cites the

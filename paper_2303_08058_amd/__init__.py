@@ -93,6 +93,10 @@ _lib.ot_fmm_plan_kernel_times.argtypes = [_P, _P, _P]
 _lib.ot_fmm_plan_kernel_times.restype = _I
 _lib.ot_fmm_multipole_batched_save.argtypes = [_P, _P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_batched_save.restype = _I
+_lib.ot_fmm_multipole_batched_full_save.argtypes = [_P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_batched_full_save.restype = _I
+_lib.ot_fmm_multipole_backward_full_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _I, _P]
+_lib.ot_fmm_multipole_backward_full_saved.restype = _I
 _lib.ot_fmm_multipole_batched_amc.argtypes = [_P, _P, _P, _P, _P, _I, _P]
 _lib.ot_fmm_multipole_batched_amc.restype = _I
 _lib.ot_fmm_multipole_backward_saved.argtypes = [_P, _P, _P, _P, _P, _P, _P, _I, _P]
@@ -337,13 +341,14 @@ class Plan:
             "ot_fmm_multipole_backward_full")
         return gM, gcom
 
-    def multipole_batched_save(self, M, com, L, Cs, sched=SCHED_AUTO, stream=None):
+    def multipole_batched_save(self, M, com, L, Cs, sched=SCHED_AUTO, stream=None, full=False):
         """Forward that also writes the target-side derivative sums Cs
-        (24, T*512) the one-pass adjoint needs."""
+        (24, T*512) the one-pass adjoint needs (full=True: of the full truncation)."""
         sm, sx, sl = self._shapes()
-        _check(_lib.ot_fmm_multipole_batched_save(
-            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
-            _dptr(Cs, (NSAVED, sl[1]), "Cs"), int(sched), _stream(stream)), "ot_fmm_multipole_batched_save")
+        fn, name = ((_lib.ot_fmm_multipole_batched_full_save, "ot_fmm_multipole_batched_full_save") if full
+                    else (_lib.ot_fmm_multipole_batched_save, "ot_fmm_multipole_batched_save"))
+        _check(fn(self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(L, sl, "L"),
+                  _dptr(Cs, (NSAVED, sl[1]), "Cs"), int(sched), _stream(stream)), name)
         return L, Cs
 
     def multipole_batched_amc(self, M, com, L, dF, sched=SCHED_AUTO, stream=None):
@@ -355,13 +360,15 @@ class Plan:
             _dptr(dF, (3, sl[1]), "dF"), int(sched), _stream(stream)), "ot_fmm_multipole_batched_amc")
         return L, dF
 
-    def multipole_backward_saved(self, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None):
-        """One-pass adjoint from the sums of multipole_batched_save (gM, gcom overwritten)."""
+    def multipole_backward_saved(self, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None, full=False):
+        """One-pass adjoint from the sums of multipole_batched_save (gM, gcom
+        overwritten; full=True: of the full truncation)."""
         sm, sx, sl = self._shapes()
-        _check(_lib.ot_fmm_multipole_backward_saved(
-            self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(gL, sl, "gL"),
-            _dptr(Cs, (NSAVED, sl[1]), "Cs"), _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"), int(sched),
-            _stream(stream)), "ot_fmm_multipole_backward_saved")
+        fn, name = ((_lib.ot_fmm_multipole_backward_full_saved, "ot_fmm_multipole_backward_full_saved") if full
+                    else (_lib.ot_fmm_multipole_backward_saved, "ot_fmm_multipole_backward_saved"))
+        _check(fn(self.handle, _dptr(M, sm, "M"), _dptr(com, sx, "com"), _dptr(gL, sl, "gL"),
+                  _dptr(Cs, (NSAVED, sl[1]), "Cs"), _dptr(gM, sm, "gM"), _dptr(gcom, sx, "gcom"), int(sched),
+                  _stream(stream)), name)
         return gM, gcom
 
     def autotune_saved(self, M, com, L, Cs, gL, gM, gcom, stream=None):
@@ -441,6 +448,14 @@ def ot_fmm_multipole_backward_saved(plan, M, com, gL, Cs, gM, gcom, sched=SCHED_
     return plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom, sched, stream)
 
 
+def ot_fmm_multipole_batched_full_save(plan, M, com, L, Cs, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_batched_save(M, com, L, Cs, sched, stream, full=True)
+
+
+def ot_fmm_multipole_backward_full_saved(plan, M, com, gL, Cs, gM, gcom, sched=SCHED_AUTO, stream=None):
+    return plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom, sched, stream, full=True)
+
+
 def ot_fmm_multipole_batched_amc(plan, M, com, L, dF, sched=SCHED_AUTO, stream=None):
     return plan.multipole_batched_amc(M, com, L, dF, sched, stream)
 
@@ -505,10 +520,9 @@ class MultipoleBatched(torch.autograd.Function):
     """L = multipole_batched(M, com) with the hand-written adjoint as backward
     (full=True: the full truncation and its adjoint).
 
-    With the total-order truncation and a gradient to compute, the forward
-    also keeps the target-side sums (24 doubles per target cell) and the
-    backward is the one-pass adjoint (save=False: plain forward, two-pass
-    adjoint).
+    With a gradient to compute, the forward also keeps the target-side sums
+    (24 doubles per target cell) and the backward is the one-pass adjoint
+    (save=False: plain forward, two-pass adjoint), for either truncation.
 
     Usage: L = MultipoleBatched.apply(M, com, plan[, full[, save]])."""
 
@@ -517,14 +531,14 @@ class MultipoleBatched(torch.autograd.Function):
         M = M.contiguous()
         com = com.contiguous()
         L = torch.empty((20, plan.T * 512), dtype=torch.float64, device=M.device)
-        use_save = bool(save) and not full and any(ctx.needs_input_grad[:2])
-        if full:
+        use_save = bool(save) and any(ctx.needs_input_grad[:2])
+        if use_save:
+            Cs = torch.empty((NSAVED, plan.T * 512), dtype=torch.float64, device=M.device)
+            plan.multipole_batched_save(M, com, L, Cs, full=full)
+            ctx.save_for_backward(M, com, Cs)
+        elif full:
             plan.multipole_batched_full(M, com, L)
             ctx.save_for_backward(M, com)
-        elif use_save:
-            Cs = torch.empty((NSAVED, plan.T * 512), dtype=torch.float64, device=M.device)
-            plan.multipole_batched_save(M, com, L, Cs)
-            ctx.save_for_backward(M, com, Cs)
         else:
             plan.multipole_batched(M, com, L)
             ctx.save_for_backward(M, com)
@@ -540,7 +554,7 @@ class MultipoleBatched(torch.autograd.Function):
             M, com, Cs = ctx.saved_tensors
             gM = torch.empty_like(M)
             gcom = torch.empty_like(com)
-            ctx.plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom)
+            ctx.plan.multipole_backward_saved(M, com, gL, Cs, gM, gcom, full=ctx.full)
         else:
             M, com = ctx.saved_tensors
             gM = torch.empty_like(M)

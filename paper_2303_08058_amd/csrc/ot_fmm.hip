@@ -498,9 +498,13 @@ bool valid_save_sched(int s)
 // Forward that also writes the target-role sums of the adjoint,
 // C'_g(i) = sum_j sum_{|b| <= 4-|g|} s_b M_b(j) G_{g+b}(X_i - X_j), 1 <= |g| <= 4
 // (= dL_a(i)/dX_i,k for g = a + e_k), 24 kept components [24][T*512].
+// FULL: the full truncation, C'_g = sum_j sum_{|b| <= 3} s_b M_b(j) G_{g+b}
+// (its orders 1..3 are L itself), derivatives to order 7.
+template <bool FULL = false>
 int fwd_save_batched(ot_fmm_plan plan, const double* M, const double* com, double* L, double* Cs, int sched,
                      hipStream_t stream)
 {
+    constexpr int kMode = FULL ? MODE_FSF_STORE : MODE_FS_STORE;
     KParams kp{};
     kp.mom = M;
     kp.pos = com;
@@ -514,13 +518,14 @@ int fwd_save_batched(ot_fmm_plan plan, const double* M, const double* com, doubl
     kp.out_stride = (long)plan->T * kSub3;
     kp.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
-    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_save ? plan->tuned_save : kSaveSched;
+    if (sched == OT_FMM_SCHED_AUTO) sched = (!FULL && plan->tuned_save) ? plan->tuned_save : kSaveSched;
     const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
     apply_order(kp, plan, sched, false);
     const int shape = sched & kShapeMask;
-    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_FS_STORE, 8>(plan, 3, kp, plan->T, pers, stream);
+    const int which = FULL ? -1 : 3;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<kMode, 8>(plan, which, kp, plan->T, pers, stream);
     if (shape == OT_FMM_SCHED_W8P2)
-        return launch_timed<MODE_FS_STORE, 8, 2>(plan, 3, kp, plan->T, pers, stream);
+        return launch_timed<kMode, 8, 2>(plan, which, kp, plan->T, pers, stream);
     return fail(OT_FMM_EINVAL, "unknown schedule for the forward with saved sums");
 }
 
@@ -557,10 +562,12 @@ int fwd_amc_batched(ot_fmm_plan plan, const double* M, const double* com, double
 
 // One-pass adjoint from the saved sums: the source-role pass over every store
 // sub-grid, whose epilogue adds the target role of the sub-grid's own cells
-// (when it is a target) from the saved sums and gL.
+// (when it is a target) from the saved sums and gL. FULL: of the full truncation.
+template <bool FULL = false>
 int bwd_saved_batched(ot_fmm_plan plan, const double* M, const double* com, const double* gL, const double* Cs,
                       double* gM, double* gcom, int sched, hipStream_t stream)
 {
+    constexpr int kMode = FULL ? MODE_B2SF_STORE : MODE_B2S_STORE;
     const long NS = (long)plan->S * kSub3, NT = (long)plan->T * kSub3;
     KParams kp{};
     kp.mom = gL;
@@ -581,13 +588,15 @@ int bwd_saved_batched(ot_fmm_plan plan, const double* M, const double* com, cons
     kp.out_stride = NS;
     kp.out_blk = nullptr;
     for (int k = 0; k < 3; ++k) kp.period[k] = plan->period[k];
-    if (sched == OT_FMM_SCHED_AUTO) sched = plan->tuned_saved_bwd ? plan->tuned_saved_bwd : kSaveSched;
+    if (sched == OT_FMM_SCHED_AUTO)
+        sched = (!FULL && plan->tuned_saved_bwd) ? plan->tuned_saved_bwd : kSaveSched;
     const bool pers = (sched & OT_FMM_SCHED_PERSISTENT) != 0;
     apply_order(kp, plan, sched, true);
     const int shape = sched & kShapeMask;
-    if (shape == OT_FMM_SCHED_W8) return launch_timed<MODE_B2S_STORE, 8>(plan, 4, kp, plan->S, pers, stream);
+    const int which = FULL ? -1 : 4;
+    if (shape == OT_FMM_SCHED_W8) return launch_timed<kMode, 8>(plan, which, kp, plan->S, pers, stream);
     if (shape == OT_FMM_SCHED_W8P2)
-        return launch_timed<MODE_B2S_STORE, 8, 2>(plan, 4, kp, plan->S, pers, stream);
+        return launch_timed<kMode, 8, 2>(plan, which, kp, plan->S, pers, stream);
     return fail(OT_FMM_EINVAL, "unknown schedule for the one-pass adjoint");
 }
 
@@ -1451,6 +1460,34 @@ int ot_fmm_multipole_backward_saved(ot_fmm_plan plan, const double* M, const dou
     if ((rc = check_saved_bwd(plan, M, com, gL, Cs, gM, gcom))) return rc;
     if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
     return bwd_saved_batched(plan, M, com, gL, Cs, gM, gcom, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole_batched_full_save(ot_fmm_plan plan, const double* M, const double* com, double* L,
+                                       double* Cs, int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!aligned8(M) || !aligned8(com) || !aligned8(L) || !aligned8(Cs))
+        return fail(OT_FMM_EINVAL, "null or misaligned (8-byte) pointer");
+    const int64_t NS = (int64_t)plan->S * kSub3, NT = (int64_t)plan->T * kSub3;
+    if (overlap(L, 20 * NT, M, 20 * NS) || overlap(L, 20 * NT, com, 3 * NS))
+        return fail(OT_FMM_EINVAL, "L overlaps an input");
+    if (overlap(Cs, 24 * NT, M, 20 * NS) || overlap(Cs, 24 * NT, com, 3 * NS) || overlap(Cs, 24 * NT, L, 20 * NT))
+        return fail(OT_FMM_EINVAL, "the saved sums overlap an input or L");
+    if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
+    return fwd_save_batched<true>(plan, M, com, L, Cs, sched, (hipStream_t)stream);
+}
+
+int ot_fmm_multipole_backward_full_saved(ot_fmm_plan plan, const double* M, const double* com, const double* gL,
+                                         const double* Cs, double* gM, double* gcom, int sched, void* stream)
+{
+    g_last_error.clear();
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if ((rc = check_saved_bwd(plan, M, com, gL, Cs, gM, gcom))) return rc;
+    if (!valid_save_sched(sched)) return fail(OT_FMM_EINVAL, "unknown schedule (W8 or W8P2, with flags)");
+    return bwd_saved_batched<true>(plan, M, com, gL, Cs, gM, gcom, sched, (hipStream_t)stream);
 }
 
 int ot_fmm_autotune_saved(ot_fmm_plan plan, const double* M, const double* com, double* L, double* Cs,

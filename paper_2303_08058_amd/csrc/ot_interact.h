@@ -476,8 +476,10 @@ enum Mode : int {
     MODE_FS_STORE = 8,    // batched forward -> L, plus the target-role sums the adjoint needs
     MODE_B2S_STORE = 9,   // adjoint from those sums: source role per store sub-grid, plus the
                           // target role of its cells from the saved sums -> gM, gX (overwrite)
-    MODE_AMC_STORE = 10   // batched forward -> L, plus the angular-momentum correction of the
+    MODE_AMC_STORE = 10,  // batched forward -> L, plus the angular-momentum correction of the
                           // force of each target cell -> dF
+    MODE_FSF_STORE = 11,  // full truncation: forward -> L, plus the target-role sums of its adjoint
+    MODE_B2SF_STORE = 12  // full truncation: one-pass adjoint from those sums -> gM, gX (overwrite)
 };
 
 constexpr int kMaxPieces = 16;  // work-list pieces (one per XCD) of a persistent launch
@@ -519,9 +521,14 @@ struct ModeTraits {
     // staged source components: the mass, or the 16 trace-reduced moments
     static constexpr int nq = (MODE == MODE_MONO_HALO) ? 1 : kNRed;
     static constexpr int nc = nq + 3;  // + centre of mass
-    static constexpr bool adjoint = (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE ||
-                                     MODE == MODE_B1F_STORE || MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE);
-    static constexpr bool source_role = (MODE == MODE_B2_STORE || MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE);
+    static constexpr bool adjoint = (MODE == MODE_B1_STORE || MODE == MODE_B2_STORE || MODE == MODE_B1F_STORE ||
+                                     MODE == MODE_B2F_STORE || MODE == MODE_B2S_STORE || MODE == MODE_B2SF_STORE);
+    static constexpr bool source_role = (MODE == MODE_B2_STORE || MODE == MODE_B2F_STORE ||
+                                         MODE == MODE_B2S_STORE || MODE == MODE_B2SF_STORE);
+    // one set of sums of orders 0..4 under the full truncation (every |b| <= 3)
+    static constexpr bool full4 = (MODE == MODE_B2F_STORE || MODE == MODE_B2SF_STORE || MODE == MODE_FSF_STORE);
+    // the target role added from saved sums in the source-role pass's epilogue
+    static constexpr bool saved_target = (MODE == MODE_B2S_STORE || MODE == MODE_B2SF_STORE);
     // the F + E sums (total order 3, and the order-4 terms of orders 1..4)
     static constexpr bool fe = (MODE == MODE_B2_STORE || MODE == MODE_B2S_STORE || MODE == MODE_FS_STORE ||
                                 MODE == MODE_AMC_STORE);
@@ -532,7 +539,7 @@ struct ModeTraits {
     static constexpr int nacc = (MODE == MODE_MONO_HALO)                             ? 20
                                 : (MODE == MODE_B1_STORE || MODE == MODE_B1F_STORE) ? 24
                                 : fe                                                ? 40
-                                : (MODE == MODE_B2F_STORE)                          ? 25
+                                : full4                                             ? 25
                                                                                     : 16;
 };
 
@@ -797,8 +804,8 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
                         radial<7>(rx, ry, rz, D);
                         const double rr[3] = {rx, ry, rz};
                         contract_full<1>(acc, q, rr, D, std::make_integer_sequence<int, 34>{});
-                    } else if constexpr (MODE == MODE_B2F_STORE) {
-                        // C_d, 0 <= |d| <= 4, every |a| <= 3
+                    } else if constexpr (T::full4) {
+                        // C_d, 0 <= |d| <= 4, every source moment (|a| <= 3 or |b| <= 3)
                         double D[8];
                         radial<7>(rx, ry, rz, D);
                         const double rr[3] = {rx, ry, rz};
@@ -857,7 +864,18 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         }
         if (half == 1) continue;  // the next pass (none after the last)
     }
-    if constexpr (MODE == MODE_FS_STORE) {
+    if constexpr (MODE == MODE_FSF_STORE) {
+        // full truncation: L is the sums of orders 0..3 (kept slots 0..15);
+        // the target-role sums C'_g, 1 <= |g| <= 4, are the kept slots 1..24
+        double L[20];
+        expand<0>(acc, L, std::make_integer_sequence<int, 20>{});
+        const long b = p.out_blk ? p.out_blk[owner] : owner;
+        const long ob = b * kSub3 + cell;
+#pragma unroll
+        for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = L[a];
+#pragma unroll
+        for (int k = 0; k < 24; ++k) p.out1[k * p.out_stride + ob] = acc[k + 1];
+    } else if constexpr (MODE == MODE_FS_STORE) {
         // L from F; the saved sums C'_g (1 <= |g| <= 4, total order 4) =
         // F_g + E_g for |g| <= 3, E_g for |g| = 4, in kept slots (F's kept
         // slot k + 1 and C's kept slot k are the same multi-index)
@@ -910,7 +928,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
         double F[20];
         if constexpr (MODE == MODE_B1_STORE || MODE == MODE_B1F_STORE) {
             expand<1>(acc, C, std::make_integer_sequence<int, 34>{});
-        } else if constexpr (MODE == MODE_B2F_STORE) {
+        } else if constexpr (T::full4) {
             // one set of sums for orders 0..4: F (orders 0..3) and C (1..4)
             expand<0>(acc, F, std::make_integer_sequence<int, 20>{});
             expand<1>(acc + 1, C, std::make_integer_sequence<int, 34>{});
@@ -934,7 +952,7 @@ __global__ void __launch_bounds__(NW * 64) k_interact(const KParams p)
             scale_inv_fact(F, std::make_integer_sequence<int, 20>{});  // gM_b = F_b / b!
 #pragma unroll
             for (int a = 0; a < 20; ++a) p.out0[a * p.out_stride + ob] = F[a];
-            if constexpr (MODE == MODE_B2S_STORE) {
+            if constexpr (T::saved_target) {
                 // the target role of the owner's cells, from the sums the
                 // forward saved: gX_k += sum_a w_a C'_{a+e_k}
                 const int t = p.store_tgt[owner];

@@ -1,6 +1,7 @@
 """The saved target-side sums of the two-launch step against the oracle
 (shared by the GPU tests): the saved component g = a + e_k of a target cell
-is the oracle's target-side derivative dL_a(i)/dX_i,k."""
+is the oracle's target-side derivative dL_a(i)/dX_i,k (of the total-order
+or, full=True, of the full truncation's L)."""
 import numpy as np
 
 import oracle
@@ -32,15 +33,15 @@ def saved_index():
     return pairs, groups
 
 
-def saved_reference(batch, M, X, tsel=None):
+def saved_reference(batch, M, X, tsel=None, full=False):
     """The oracle's values of the saved sums for targets tsel, (24, n*512),
     and the magnitudes of their terms."""
-    D, A = oracle.batched_forward_tgrad(batch, M, X, tsel=tsel, want_abs=True)
+    D, A = oracle.batched_forward_tgrad(batch, M, X, tsel=tsel, want_abs=True, full=full)
     pairs, _ = saved_index()
     return (np.stack([D[a, k] for a, k in pairs]), np.stack([A[a, k] for a, k in pairs]))
 
 
-def check_saved(got, batch, M, X, what, tsel=None):
-    ref, A = saved_reference(batch, M, X, tsel)
+def check_saved(got, batch, M, X, what, tsel=None, full=False):
+    ref, A = saved_reference(batch, M, X, tsel, full)
     _, groups = saved_index()
     return assert_parity(got, ref, TOL, groups=groups, what=what, A=A)

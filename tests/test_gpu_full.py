@@ -14,6 +14,7 @@ sys.path.insert(0, os.path.dirname(__file__))
 import oracle  # noqa: E402
 import synthetic  # noqa: E402
 from parity import assert_parity  # noqa: E402
+from saved_sums import check_saved  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -154,15 +155,16 @@ def test_full_adjoint_open_lattice_and_autograd(ot):
     sel = np.array([0, 13, 26], np.int32)
     gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, ssel=sel, full=True)
     plan = ot.Plan.from_batch(batch)
-    Mt = _dev(M).requires_grad_(True)
-    Xt = _dev(X).requires_grad_(True)
-    L = ot.multipole(Mt, Xt, plan, full=True)
-    (L * _dev(w)).sum().backward()
     cols = lambda a: a.reshape(a.shape[0], -1, SUB3)[:, sel].reshape(a.shape[0], -1)
-    assert_parity(cols(_host(Mt.grad)), gM_ref, TOL, what="autograd full gM")
-    assert_parity(cols(_host(Xt.grad)), gX_ref, TOL, what="autograd full gX")
     ref_L = oracle.batched_forward(batch, M, X, tsel=sel, full=True)
-    assert_parity(cols(_host(L.detach())), ref_L, TOL, what="autograd full L")
+    for save in (True, False):  # one-pass adjoint from saved sums, or two passes
+        Mt = _dev(M).requires_grad_(True)
+        Xt = _dev(X).requires_grad_(True)
+        L = ot.multipole(Mt, Xt, plan, full=True, save=save)
+        (L * _dev(w)).sum().backward()
+        assert_parity(cols(_host(Mt.grad)), gM_ref, TOL, what="autograd full gM save=%s" % save)
+        assert_parity(cols(_host(Xt.grad)), gX_ref, TOL, what="autograd full gX save=%s" % save)
+        assert_parity(cols(_host(L.detach())), ref_L, TOL, what="autograd full L save=%s" % save)
 
 
 def test_full_adjoint_config4_sampled(ot):
@@ -239,6 +241,14 @@ def test_full_config5_default_schedule_sampled(ot):
     plan.multipole_backward_full(Md, Xd, wd, gM, gX)
     torch.cuda.synchronize()
     assert bool(torch.isfinite(L).all()) and bool(torch.isfinite(gM).all()) and bool(torch.isfinite(gX).all())
+    # the two-launch step (forward with saved sums, one-pass adjoint) as timed
+    Ls, Cs = _empty(20, NT), _empty(24, NT)
+    plan.multipole_batched_save(Md, Xd, Ls, Cs, full=True)
+    gMs, gXs = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_saved(Md, Xd, wd, Cs, gMs, gXs, full=True)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(Ls).all()) and bool(torch.isfinite(Cs).all())
+    assert bool(torch.isfinite(gMs).all()) and bool(torch.isfinite(gXs).all())
     rng = np.random.default_rng(2006)
     miss = batch["missing_targets"]
     sel = np.sort(np.concatenate([rng.choice(miss, 2, replace=False),
@@ -253,3 +263,100 @@ def test_full_config5_default_schedule_sampled(ot):
     cols3 = lambda t: t.reshape(t.shape[0], -1, SUB3)[:, sub].reshape(t.shape[0], -1).cpu().numpy()
     print("config5 full gM", assert_parity(cols3(gM), gM_ref, TOL, what="config5 full gM"))
     print("config5 full gX", assert_parity(cols3(gX), gX_ref, TOL, what="config5 full gX"))
+    print("config5 full saved-step L", assert_parity(cols(Ls), ref, TOL, what="config5 full saved-step L", A=A))
+    print("config5 full one-pass gM", assert_parity(cols3(gMs), gM_ref, TOL, what="config5 full one-pass gM"))
+    print("config5 full one-pass gX", assert_parity(cols3(gXs), gX_ref, TOL, what="config5 full one-pass gX"))
+    csel = sel[:2]
+    ci = torch.from_numpy(csel).long().cuda()
+    cs_cols = Cs.reshape(24, -1, SUB3)[:, ci].reshape(24, -1).cpu().numpy()
+    check_saved(cs_cols, batch, M, X, "config5 full saved sums", tsel=csel, full=True)
+
+
+# ---------------------------------------------------------------------------
+# the two-launch step of the full truncation: forward with the target-side
+# sums saved, one-pass adjoint from them
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sched", [0, 1, 3, 0x11, 0x13, 0x23, 0x33])
+def test_full_saved_step_small_periodic_with_missing(ot, small_adjoint_case, sched):
+    batch, M, X, w, gM_ref, gX_ref = small_adjoint_case
+    plan = ot.Plan.from_batch(batch)
+    NS, NT = batch["S"] * SUB3, batch["T"] * SUB3
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    L, Cs = _empty(20, NT), _empty(24, NT)
+    plan.multipole_batched_save(Md, Xd, L, Cs, sched=sched, full=True)
+    Lh, Csh = _host(L), _host(Cs)
+    ref, A = oracle.batched_forward(batch, M, X, want_abs=True, full=True)
+    assert_parity(Lh, ref, TOL, what="full saved-step L", A=A)
+    print("full saved sums", check_saved(Csh, batch, M, X, "full saved sums", full=True))
+    gM, gX = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, sched=sched, full=True)
+    gMh, gXh = _host(gM), _host(gX)
+    print("full one-pass gM", assert_parity(gMh, gM_ref, TOL, what="full one-pass gM"))
+    print("full one-pass gX", assert_parity(gXh, gX_ref, TOL, what="full one-pass gX"))
+    L2, Cs2, gM2, gX2 = _empty(20, NT), _empty(24, NT), _empty(20, NS), _empty(3, NS)
+    plan.multipole_batched_save(Md, Xd, L2, Cs2, sched=sched, full=True)
+    plan.multipole_backward_saved(Md, Xd, wd, Cs2, gM2, gX2, sched=sched, full=True)
+    assert np.array_equal(_host(L2), Lh) and np.array_equal(_host(Cs2), Csh)
+    assert np.array_equal(_host(gM2), gMh) and np.array_equal(_host(gX2), gXh)
+
+
+def test_full_saved_step_open_subset_of_targets(ot):
+    """Open lattice, three targets with knocked-out neighbours: store
+    sub-grids that are not targets have no target role."""
+    rng = synthetic._rng(225)
+    M, X = synthetic.store_field(3, rng, 2.0, 3.0, 0.6, sep=6.0)
+    lat = synthetic.lattice_batch(3, periodic=False)
+    tg = np.array([13, 4, 22], np.int32)
+    nbr = lat["nbr"][tg].copy()
+    nbr[0, [5, 21]] = -1
+    nbr[1, 14] = -1
+    batch = {"S": 27, "T": 3, "tgt": tg, "nbr": nbr, "shift": None, "period": None}
+    w = synthetic.weights(3, 226)
+    plan = ot.Plan.from_batch(batch)
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    L, Cs = _empty(20, 3 * SUB3), _empty(24, 3 * SUB3)
+    plan.multipole_batched_save(Md, Xd, L, Cs, full=True)
+    check_saved(_host(Cs), batch, M, X, "full saved sums open", full=True)
+    gM, gX = _empty(20, 27 * SUB3), _empty(3, 27 * SUB3)
+    plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, full=True)
+    gM_ref, gX_ref = oracle.batched_backward(batch, M, X, w, full=True)
+    assert_parity(_host(gM), gM_ref, TOL, what="full open gM")
+    assert_parity(_host(gX), gX_ref, TOL, what="full open gX")
+
+
+def test_full_saved_moment_gradient_equals_the_two_pass_adjoint_bitwise(ot):
+    batch, M, X = synthetic.batched_config(3, 227, missing_frac=0.3)
+    w = synthetic.weights(batch["T"], 228)
+    plan = ot.Plan.from_batch(batch)
+    NS, NT = batch["S"] * SUB3, batch["T"] * SUB3
+    Md, Xd, wd = _dev(M), _dev(X), _dev(w)
+    L, Cs = _empty(20, NT), _empty(24, NT)
+    plan.multipole_batched_save(Md, Xd, L, Cs, sched=3, full=True)
+    gM, gX = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, sched=3, full=True)
+    gM2, gX2 = _empty(20, NS), _empty(3, NS)
+    plan.multipole_backward_full(Md, Xd, wd, gM2, gX2, sched=ot.sched_bwd(1, 3))
+    assert np.array_equal(_host(gM), _host(gM2))
+    gX_ref = oracle.batched_backward(batch, M, X, w, full=True)[1]
+    assert_parity(_host(gX), gX_ref, TOL, what="full gX 3^3")
+
+
+def test_full_saved_rejects_bad_arguments(ot):
+    batch, M, X = synthetic.batched_config(2, 229)
+    plan = ot.Plan.from_batch(batch)
+    NS, NT = batch["S"] * SUB3, batch["T"] * SUB3
+    Md, Xd, wd = _dev(M), _dev(X), _dev(synthetic.weights(batch["T"], 230))
+    L, Cs, gM, gX = _empty(20, NT), _empty(24, NT), _empty(20, NS), _empty(3, NS)
+    for bad in (2, 0x12, 7, 0x10, 0x40 | 1, 1 << 8):
+        with pytest.raises(ot.OtFmmError):
+            plan.multipole_batched_save(Md, Xd, L, Cs, sched=bad, full=True)
+        with pytest.raises(ot.OtFmmError):
+            plan.multipole_backward_saved(Md, Xd, wd, Cs, gM, gX, sched=bad, full=True)
+    import torch
+    flat = torch.zeros(44 * NT, dtype=torch.float64, device="cuda")
+    with pytest.raises(ot.OtFmmError):  # the sums overlapping L
+        plan.multipole_batched_save(Md, Xd, flat[:20 * NT].view(20, NT), flat[10 * NT:34 * NT].view(24, NT),
+                                    sched=3, full=True)
+    with pytest.raises(ot.OtFmmError):  # gcom overlapping the sums
+        plan.multipole_backward_saved(Md, Xd, wd, flat[:24 * NT].view(24, NT), gM,
+                                      flat[:3 * NS].view(3, NS), sched=3, full=True)

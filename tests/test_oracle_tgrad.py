@@ -3,7 +3,8 @@ D[a, k](i) = dL_a(i)/dX_i,k with the sources' centres held fixed (the sums
 the one-pass adjoint saves in the forward): complex-step derivatives of the
 plain forward sum with only the target cell's centre perturbed, equality of
 the entries that name the same derivative of G (a + e_k = a' + e_k'), and
-Laplace's equation. CPU only."""
+Laplace's equation; for the total-order truncation and the full one (every
+source moment for every output order). CPU only."""
 import numpy as np
 import pytest
 
@@ -29,10 +30,11 @@ def _open_case():
     return {"S": 27, "T": 2, "tgt": tg, "nbr": nbr, "shift": None, "period": None}, M, X
 
 
+@pytest.mark.parametrize("full", [False, True])
 @pytest.mark.parametrize("case", ["periodic", "open"])
-def test_complex_step_of_the_forward(case):
+def test_complex_step_of_the_forward(case, full):
     batch, M, X = _periodic_case() if case == "periodic" else _open_case()
-    D, A = oracle.batched_forward_tgrad(batch, M, X, want_abs=True)
+    D, A = oracle.batched_forward_tgrad(batch, M, X, want_abs=True, full=full)
     h = 1e-30
     for t, cell in [(0, 0), (0, 300), (1, 511), (batch["T"] - 1, 137)]:
         c = int(batch["tgt"][t]) * SUB3 + cell
@@ -40,15 +42,16 @@ def test_complex_step_of_the_forward(case):
         for k in range(3):
             Xim = np.zeros_like(X)
             Xim[k, c] = h
-            _, Lim = oracle.batched_forward_cs(batch, M, X, Xim, tsel=[t])
+            _, Lim = oracle.batched_forward_cs(batch, M, X, Xim, tsel=[t], full=full)
             cs = Lim[:, cell] / h
             err = np.abs(cs - D[:, k, col])
             assert np.all(err <= 1e-13 * A[:, k, col] + 1e-300), (case, t, cell, k, err.max())
 
 
-def test_entries_naming_the_same_derivative_are_equal():
+@pytest.mark.parametrize("full", [False, True])
+def test_entries_naming_the_same_derivative_are_equal(full):
     batch, M, X = _periodic_case()
-    D = oracle.batched_forward_tgrad(batch, M, X)
+    D = oracle.batched_forward_tgrad(batch, M, X, full=full)
     exps = [oracle.multi_index(g) for g in range(20)]
     index = {tuple(e): g for g, e in enumerate(exps)}
     npair = 0
@@ -66,10 +69,11 @@ def test_entries_naming_the_same_derivative_are_equal():
     assert npair > 0 and index[(0, 0, 0)] == 0
 
 
-def test_laplace_trace():
+@pytest.mark.parametrize("full", [False, True])
+def test_laplace_trace(full):
     """sum_k D[g + e_k, k] = sum_beta s_beta M_beta lap G_{g+beta} = 0."""
     batch, M, X = _periodic_case()
-    D, A = oracle.batched_forward_tgrad(batch, M, X, want_abs=True)
+    D, A = oracle.batched_forward_tgrad(batch, M, X, want_abs=True, full=full)
     exps = [tuple(oracle.multi_index(g)) for g in range(20)]
     index = {e: g for g, e in enumerate(exps)}
     for g, e in enumerate(exps):
@@ -84,3 +88,21 @@ def test_laplace_trace():
             tr += D[a, k]
             scale += A[a, k]
         assert np.all(np.abs(tr) <= 1e-13 * scale + 1e-300), (e, np.abs(tr).max())
+
+
+def test_full_orders_one_to_three_are_the_full_forward():
+    """Under the full truncation every output order keeps every source
+    moment, so D[a, k] for |a| <= 2 is the full forward's L_{a+e_k}."""
+    batch, M, X = _periodic_case()
+    D = oracle.batched_forward_tgrad(batch, M, X, full=True)
+    L, A = oracle.batched_forward(batch, M, X, want_abs=True, full=True)
+    exps = [tuple(oracle.multi_index(g)) for g in range(20)]
+    index = {e: g for g, e in enumerate(exps)}
+    for a, e in enumerate(exps):
+        if sum(e) > 2:
+            continue
+        for k in range(3):
+            ek = list(e)
+            ek[k] += 1
+            g = index[tuple(ek)]
+            assert np.all(np.abs(D[a, k] - L[g]) <= 1e-13 * A[g] + 1e-300), (e, k)
