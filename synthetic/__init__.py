@@ -331,3 +331,42 @@ def config4(n=8):
 def config5(n=32):
     return batched_config(n, 1005, missing_frac=0.20, sigma_choices=[2.0, 4.0],
                           q_range=(0.3, 1.0))
+
+
+def device_lattice_store(n, seed, device="cuda", chunk=8192):
+    """A store of n^3 sub-grids (ids as in lattice_batch) generated on the
+    device, for stores too large to build on the host: cell centres jittered
+    by U[-0.1, 0.1] about the lattice points (h = 1), mass m ~ U[0.5, 1.5],
+    raw moments about the centre of mass with realistic magnitudes for a cell
+    of unit size -- dipole m N(0, 1e-3), second moments m (delta_ab / 12 +
+    0.02 N(0, 1)), third moments 0.005 m N(0, 1). Returns torch tensors
+    M (20, n^3*512) and X (3, n^3*512), FP64, seeded (torch's generator on
+    the device, one chunk of sub-grids after the other)."""
+    import torch
+
+    S = n ** 3
+    NS = S * SUB3
+    M = torch.empty((NM, NS), dtype=torch.float64, device=device)
+    X = torch.empty((3, NS), dtype=torch.float64, device=device)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    c = torch.arange(SUB3, device=device)
+    cell = torch.stack([c % SUB, (c // SUB) % SUB, c // (SUB * SUB)]).to(torch.float64)  # (3, 512)
+    diag = torch.zeros(6, 1, dtype=torch.float64, device=device)
+    diag[[0, 3, 5]] = 1.0 / 12.0  # xx, yy, zz among xx, xy, xz, yy, yz, zz
+    for s0 in range(0, S, chunk):
+        s1 = min(S, s0 + chunk)
+        k = s1 - s0
+        sid = torch.arange(s0, s1, device=device)
+        sc = torch.stack([sid % n, (sid // n) % n, sid // (n * n)]).to(torch.float64)  # (3, k)
+        pos = (SUB * sc[:, :, None] + cell[:, None, :] + 0.5).reshape(3, k * SUB3)
+        pos += (torch.rand((3, k * SUB3), generator=g, dtype=torch.float64, device=device) - 0.5) * 0.2
+        m = 0.5 + torch.rand((1, k * SUB3), generator=g, dtype=torch.float64, device=device)
+        z = torch.randn((NM - 1, k * SUB3), generator=g, dtype=torch.float64, device=device)
+        cols = slice(s0 * SUB3, s1 * SUB3)
+        X[:, cols] = pos
+        M[0:1, cols] = m
+        M[1:4, cols] = m * 1e-3 * z[0:3]
+        M[4:10, cols] = m * (diag + 0.02 * z[3:9])
+        M[10:20, cols] = m * 0.005 * z[9:19]
+    return M, X
