@@ -122,6 +122,13 @@ def test_kernels_reject_null_and_misaligned_pointers(lib):
         assert fn(base + 4, base, base, None) == -1
     lib.ot_fmm_multipole_batched.argtypes = [P, P, P, P, ctypes.c_int, P]
     assert lib.ot_fmm_multipole_batched(None, None, None, None, 0, None) == -1
+    for fn in (lib.ot_fmm_multipole_batched_save, lib.ot_fmm_multipole_batched_full_save,
+               lib.ot_fmm_multipole_batched_amc):
+        fn.argtypes = [P, P, P, P, P, ctypes.c_int, P]
+        assert fn(None, None, None, None, None, 0, None) == -1
+    for fn in (lib.ot_fmm_multipole_backward_saved, lib.ot_fmm_multipole_backward_full_saved):
+        fn.argtypes = [P, P, P, P, P, P, P, ctypes.c_int, P]
+        assert fn(None, None, None, None, None, None, None, 0, None) == -1
     for fn in (lib.ot_fmm_coarse_fine, lib.ot_fmm_coarse_fine_full):
         fn.argtypes = [P, P, P, P, P, P]
         assert fn(None, None, None, None, None, None) == -1
