@@ -66,6 +66,8 @@ k_coarse_fine(const CoarseParams p)
     constexpr int kSlotVals = kNc * 64;
     __shared__ double s_src[Sh::batch * kSlotVals];
     __shared__ int s_slot[Sh::batch];
+    __shared__ int4 s_ent[Sh::batch];        // the batch's entries {slot, coarse node, octant, -}
+    __shared__ double s_shift[Sh::batch][3];  // and the periodic shift of each slot
     static_assert(NW != 8 || kNa * kSub3 <= Sh::batch * kSlotVals, "epilogue reuses the staging buffer");
     const int tid = threadIdx.x;
     const int4 it = p.items[blockIdx.x];  // uniform
@@ -83,27 +85,42 @@ k_coarse_fine(const CoarseParams p)
         const int nb = (it.w - b0 < Sh::batch) ? it.w - b0 : Sh::batch;
         const int4* ent = p.entries + it.z + b0;
         __syncthreads();  // the previous batch is no longer read
-        for (int v = tid; v < nb * kSlotVals; v += NW * 64) {
-            const int b = v / kSlotVals, r = v - b * kSlotVals;
-            const int k = r >> 6, J = r & 63;
-            const int4 e = ent[b];
-            const int o = e.z;
-            const int cx = J & 3, cy = (J >> 2) & 3, cz = J >> 4;
-            const int pc = (cx + 4 * (o & 1)) + 8 * (cy + 4 * ((o >> 1) & 1)) + 64 * (cz + 4 * (o >> 2));
-            const long jj = (long)e.y * kSub3 + pc;
-            double val;
-            if (k < 3) {
-                const int packed = p.rel[(long)t * 27 + e.x].z;
-                const double sh = (double)(int)(int8_t)((packed >> (8 * k)) & 0xff) * p.period[k];
-                val = p.pos_c[k * p.c_stride + jj] + sh;
-            } else {
-                const int cP = c_red_src[k - 3][0], cS = c_red_src[k - 3][1];
-                val = c_scale_fwd[cP] * p.mom_c[cP * p.c_stride + jj];
-                if (cS >= 0) val -= c_scale_fwd[cS] * p.mom_c[cS * p.c_stride + jj];
-            }
-            s_src[v] = val;
+        if (tid < nb) {
+            // the batch's entries and shifts, read once
+            const int4 e = ent[tid];
+            const int packed = p.rel[(long)t * 27 + e.x].z;
+            s_ent[tid] = e;
+            s_slot[tid] = e.x;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                s_shift[tid][k] = (double)(int)(int8_t)((packed >> (8 * k)) & 0xff) * p.period[k];
         }
-        if (tid < nb) s_slot[tid] = ent[tid].x;
+        __syncthreads();
+        // a thread's values four at a time (their loads in flight together;
+        // no load depends on another)
+        constexpr int kIter = (Sh::batch * kSlotVals + NW * 64 - 1) / (NW * 64);
+#pragma unroll 4
+        for (int i = 0; i < kIter; ++i) {
+            const int v = tid + i * NW * 64;
+            if (v < nb * kSlotVals) {
+                const int b = v / kSlotVals, r = v - b * kSlotVals;
+                const int k = r >> 6, J = r & 63;
+                const int4 e = s_ent[b];
+                const int o = e.z;
+                const int cx = J & 3, cy = (J >> 2) & 3, cz = J >> 4;
+                const int pc = (cx + 4 * (o & 1)) + 8 * (cy + 4 * ((o >> 1) & 1)) + 64 * (cz + 4 * (o >> 2));
+                const long jj = (long)e.y * kSub3 + pc;
+                double val;
+                if (k < 3) {
+                    val = p.pos_c[k * p.c_stride + jj] + s_shift[b][k];
+                } else {
+                    const int cP = c_red_src[k - 3][0], cS = c_red_src[k - 3][1];
+                    val = c_scale_fwd[cP] * p.mom_c[cP * p.c_stride + jj];
+                    if (cS >= 0) val -= c_scale_fwd[cS] * p.mom_c[cS * p.c_stride + jj];
+                }
+                s_src[v] = val;
+            }
+        }
         __syncthreads();
         // one loop over the lane's (slot, coarse cell) pairs of the batch, so
         // that a wavefront runs as many trips as its busiest lane has pairs;
